@@ -1,0 +1,161 @@
+/*
+ * sw.h -- C ABI of the batched Smith-Waterman library (gfx950 / MI355X).
+ *
+ * The library aligns many candidate protein pairs of uneven length with local
+ * (Smith-Waterman) alignment, the BLOSUM62 matrix and affine (Gotoh) gaps, in
+ * exact int32 arithmetic, and returns for every pair the best score and the
+ * start and end of the aligned region in both sequences.  This is the batch
+ * alignment stage of the paper's pipeline (section "Protein similarity search
+ * pipeline", stage (ii); section "Load balancing techniques": the full m x n
+ * matrix is computed for every pair, so the cost of a pair is m*n).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named *_dev are device pointers (HBM of the current HIP device);
+ *    every other pointer is host memory.  The caller owns all buffers; the
+ *    library keeps no caller pointer after the work it enqueued completes.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *    asynchronously; results are valid once the caller has synchronised it.
+ *  - Every function returns an int status (SW_OK or a negative SW_E* code);
+ *    no C++ exception crosses the interface.
+ *  - Residues are ASCII letters of the 24-symbol BLOSUM62 alphabet
+ *    A R N D C Q E G H I L K M F P S T W Y V B Z X *  (upper case only).
+ *  - A gap run of k residues costs gap_open + (k-1)*gap_extend, with
+ *    1 <= gap_open <= 2^20 and 0 <= gap_extend <= gap_open (the paper's
+ *    program-parameter table, section "Similarity search at scale", uses
+ *    separate open and extension penalties; this model is Gotoh's).
+ *  - Tie rule (the paper does not fix one): the end is the lexicographically
+ *    smallest (query, reference) cell reaching the best score; the start is
+ *    the largest (query, then reference) start among optimal alignments that
+ *    end there.  Coordinates are 0-based and inclusive; score 0 reports all
+ *    coordinates as -1.
+ */
+#ifndef SW_H
+#define SW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SW_API __attribute__((visibility("default")))
+#else
+#define SW_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SW_OK 0
+#define SW_EINVAL (-1)    /* null pointer, negative size, bad scoring, bad flags */
+#define SW_ERANGE (-2)    /* pair index outside [0, n_seqs) or sequence longer than SW_MAX_SEQ_LEN */
+#define SW_ECODE (-3)     /* a residue that is not a symbol of the alphabet */
+#define SW_ENOMEM (-4)    /* device workspace or caller buffer too small */
+#define SW_EDEVICE (-5)   /* a HIP runtime error (see sw_last_device_error) */
+#define SW_ETIMEOUT (-6)  /* a wait ran out of time */
+#define SW_EAGAIN (-7)    /* serving: the request is not admissible right now */
+#define SW_ECANCELED (-8) /* serving: the server was shut down */
+
+#define SW_MAX_SEQ_LEN 65535 /* keeps coordinates in 16 bits and scores far below 2^31 */
+
+/* Result of one pair; 20 bytes, fields in this order. */
+typedef struct {
+    int32_t score;
+    int32_t q_start, q_end;
+    int32_t r_start, r_end;
+} sw_result;
+
+typedef struct {
+    int32_t matrix_id;  /* 0 = BLOSUM62, the only matrix */
+    int32_t gap_open;   /* cost of the first residue of a gap run */
+    int32_t gap_extend; /* cost of every further residue of the run */
+} sw_scoring;
+
+/* flags of sw_batch_align */
+#define SW_PERSISTENT 0u /* default: one persistent launch over a device work queue, replayed as a HIP graph */
+#define SW_PLAIN 1u      /* one launch per length bucket, static work split, no queue, no graph */
+#define SW_VALIDATE 2u   /* synchronise before returning and report SW_ERANGE / SW_ECODE found on the device */
+#define SW_NO_GRAPH 4u   /* persistent form without HIP-graph capture */
+
+/*
+ * Bytes a packed buffer needs for n_residues residues (header, two residue
+ * planes, guard and slack).
+ */
+SW_API size_t sw_packed_bytes(int64_t n_residues);
+
+/*
+ * Encode a concatenated ASCII buffer of n_residues residues (device memory)
+ * into the library's packed 5-bit form: a 4-bit plane (8 residues per 32-bit
+ * word) plus a 1-bit plane (32 residues per word), see DESIGN notes in the
+ * source.  Residue positions are unchanged, so the same int64 offsets index
+ * sequences in the ASCII and in the packed buffer.  packed_cap must be at
+ * least sw_packed_bytes(n_residues).  Letters outside the alphabet are stored
+ * as a padding symbol that never aligns; they are reported as SW_ECODE by the
+ * next sw_check on this device or by sw_batch_align with SW_VALIDATE.
+ * Errors: SW_EINVAL (null pointer, n_residues < 0), SW_ENOMEM (packed_cap too
+ * small), SW_EDEVICE.
+ */
+SW_API int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, size_t packed_cap,
+            void* stream);
+
+/*
+ * Align n_pairs candidate pairs.
+ *   packed_dev    buffer written by sw_pack
+ *   offsets_dev   int64[n_seqs + 1]: sequence k is residues offsets[k] ..
+ *                 offsets[k+1]-1 of the packed buffer (non-decreasing)
+ *   pairs_dev     int32[2 * n_pairs]: (query index, reference index) per pair
+ *   scoring       host struct (see above)
+ *   out_dev       sw_result[n_pairs], written in pair order
+ *   flags         SW_PERSISTENT (0) | SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH
+ * A pair with an index outside [0, n_seqs) or a sequence longer than
+ * SW_MAX_SEQ_LEN gets score -1 and coordinates -1 and raises SW_ERANGE on the
+ * next check; an empty sequence gives score 0.  n_pairs == 0 does nothing.
+ * Errors returned directly: SW_EINVAL, SW_ENOMEM, SW_EDEVICE; with
+ * SW_VALIDATE the call synchronises `stream` and also returns SW_ERANGE or
+ * SW_ECODE.  The SW_PLAIN form reads the bucket sizes back to the host (one
+ * synchronisation of `stream` inside the call).
+ */
+SW_API int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs,
+                   const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring,
+                   sw_result* out_dev, void* stream, uint32_t flags);
+
+/*
+ * Synchronise `stream`, then return and clear the device-detected errors
+ * (SW_ERANGE, SW_ECODE) raised by earlier calls on the current device.
+ */
+SW_API int sw_check(void* stream);
+
+/*
+ * Kernel shape used by later calls on the current device.  rows_per_lane is
+ * the number of query rows each lane keeps in registers (16 or 32);
+ * inter_max_len is the longest pair (max of both lengths, 64..1024) that is
+ * aligned one pair per lane, longer pairs get one 64-lane wave each;
+ * blocks_per_cu sets the persistent grid (1..8).  Any field <= 0 keeps the
+ * current value.  Results never depend on these values.
+ */
+typedef struct {
+    int32_t rows_per_lane;
+    int32_t inter_max_len;
+    int32_t blocks_per_cu;
+} sw_tuning;
+SW_API int sw_set_tuning(const sw_tuning* t);
+SW_API int sw_get_tuning(sw_tuning* t);
+
+/*
+ * The library's substitution matrix in the alphabet order above
+ * (scores[24*q + r], query symbol q, reference symbol r) and the alphabet
+ * itself (25 bytes including the terminating zero).  Host memory.
+ */
+SW_API int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters);
+
+/* Text of a status code; never NULL. */
+SW_API const char* sw_strerror(int status);
+
+/* Text of the last HIP runtime error seen by the library on this thread. */
+SW_API const char* sw_last_device_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SW_H */

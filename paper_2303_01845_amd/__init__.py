@@ -1,0 +1,180 @@
+"""Python binding of the batched Smith-Waterman library (include/sw.h).
+
+Argument marshalling only: every step of the alignment path runs in the HIP
+kernels of ``libsw_hip.so``.  PyTorch supplies device memory and streams.  If
+the library is not built, every entry point raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsw_hip.so")
+
+SW_OK = 0
+SW_EINVAL = -1
+SW_ERANGE = -2
+SW_ECODE = -3
+SW_ENOMEM = -4
+SW_EDEVICE = -5
+SW_ETIMEOUT = -6
+SW_EAGAIN = -7
+SW_ECANCELED = -8
+MAX_SEQ_LEN = 65535
+
+PERSISTENT = 0
+PLAIN = 1
+VALIDATE = 2
+NO_GRAPH = 4
+
+# every function the C header declares
+EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_check", "sw_set_tuning",
+           "sw_get_tuning", "sw_matrix", "sw_strerror", "sw_last_device_error")
+
+
+class SwError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        L = _lib
+        msg = L.sw_strerror(status).decode() if L is not None else str(status)
+        if status == SW_EDEVICE and L is not None:
+            msg += " (" + L.sw_last_device_error().decode() + ")"
+        super().__init__("%s: %s [%d]" % (where, msg, status))
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("matrix_id", ctypes.c_int32), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("inter_max_len", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsw_hip.so is not built (run __graft_entry__.build() or "
+                              "python paper_2303_01845_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.sw_packed_bytes.argtypes = [ctypes.c_int64]
+        L.sw_packed_bytes.restype = ctypes.c_size_t
+        L.sw_pack.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                              ctypes.c_void_p]
+        L.sw_batch_align.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+        L.sw_check.argtypes = [ctypes.c_void_p]
+        L.sw_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.sw_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.sw_matrix.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_char_p]
+        L.sw_strerror.argtypes = [ctypes.c_int]
+        L.sw_strerror.restype = ctypes.c_char_p
+        L.sw_last_device_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != SW_OK:
+        raise SwError(status, where)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def packed_bytes(n_residues: int) -> int:
+    return int(lib().sw_packed_bytes(int(n_residues)))
+
+
+def pack(ascii, stream=None):
+    """ASCII residues (uint8 tensor on the GPU, or bytes/numpy, copied there)
+    -> packed device buffer (uint8 tensor)."""
+    import torch
+    if not isinstance(ascii, torch.Tensor):
+        ascii = torch.from_numpy(np.frombuffer(bytes(ascii), dtype=np.uint8).copy()
+                                 if not isinstance(ascii, np.ndarray) else ascii.astype(np.uint8))
+    if not ascii.is_cuda:
+        ascii = ascii.to("cuda", non_blocking=False)
+    ascii = ascii.contiguous()
+    n = ascii.numel()
+    cap = packed_bytes(n)
+    out = torch.empty(cap, dtype=torch.uint8, device=ascii.device)
+    _check(lib().sw_pack(ctypes.c_void_p(ascii.data_ptr() if n else 0), n,
+                         ctypes.c_void_p(out.data_ptr()), cap, _stream_ptr(stream)), "sw_pack")
+    return out
+
+
+def align(packed, offsets, pairs, gap_open: int = 11, gap_extend: int = 1, flags: int = PERSISTENT,
+          out=None, stream=None):
+    """Align every (query, reference) pair.  ``packed`` from ``pack``;
+    ``offsets`` int64 [n_seqs+1] and ``pairs`` int32 [n_pairs, 2] on the GPU.
+    Returns int32 [n_pairs, 5] on the GPU: score, q_start, q_end, r_start, r_end."""
+    import torch
+    n_pairs = int(pairs.shape[0]) if pairs.dim() == 2 else int(pairs.numel() // 2)
+    if out is None:
+        out = torch.empty((n_pairs, 5), dtype=torch.int32, device=pairs.device)
+    assert offsets.dtype == torch.int64 and pairs.dtype == torch.int32 and out.dtype == torch.int32
+    assert offsets.is_contiguous() and pairs.is_contiguous() and out.is_contiguous()
+    sc = Scoring(0, int(gap_open), int(gap_extend))
+    _check(lib().sw_batch_align(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                int(offsets.numel()) - 1, ctypes.c_void_p(pairs.data_ptr()), n_pairs,
+                                ctypes.byref(sc), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream),
+                                int(flags)), "sw_batch_align")
+    return out
+
+
+def check(stream=None):
+    """Synchronise and raise for device-detected errors (SW_ERANGE / SW_ECODE)."""
+    _check(lib().sw_check(_stream_ptr(stream)), "sw_check")
+
+
+def set_tuning(rows_per_lane: int = 0, inter_max_len: int = 0, blocks_per_cu: int = 0):
+    _check(lib().sw_set_tuning(ctypes.byref(Tuning(rows_per_lane, inter_max_len, blocks_per_cu))),
+           "sw_set_tuning")
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(lib().sw_get_tuning(ctypes.byref(t)), "sw_get_tuning")
+    return {"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
+            "blocks_per_cu": t.blocks_per_cu}
+
+
+def matrix():
+    """(int8 [24, 24] scores, alphabet string) as compiled into the library."""
+    scores = np.zeros(24 * 24, dtype=np.int8)
+    letters = ctypes.create_string_buffer(25)
+    _check(lib().sw_matrix(0, scores.ctypes.data, letters), "sw_matrix")
+    return scores.reshape(24, 24), letters.value.decode()
+
+
+class Batch:
+    """Sequences resident on the GPU (packed) plus their offsets."""
+
+    def __init__(self, ascii: np.ndarray, offsets: np.ndarray, stream=None):
+        import torch
+        self.offsets = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).cuda()
+        a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).cuda()
+        self.packed = pack(a, stream)
+        self.n_residues = int(a.numel())
+
+    def align(self, pairs, gap_open: int = 11, gap_extend: int = 1, flags: int = PERSISTENT,
+              out=None, stream=None):
+        import torch
+        if not isinstance(pairs, torch.Tensor):
+            pairs = torch.from_numpy(np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)).cuda()
+        return align(self.packed, self.offsets, pairs, gap_open, gap_extend, flags, out, stream)

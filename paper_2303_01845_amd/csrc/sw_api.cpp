@@ -1,0 +1,484 @@
+// Host side of the C ABI declared in include/sw.h: argument checks, the
+// per-device workspace, the work-cell orderings, HIP-graph replay of the
+// persistent form and the per-bucket launch series of the plain form.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "sw_internal.h"
+
+using namespace swk;
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int dev_error(hipError_t e, const char* what)
+{
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+    return SW_EDEVICE;
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) return dev_error(_e, what); \
+    } while (0)
+
+// Cells, ranks and the buckets of the plain form for one (R, inter_max_len).
+struct Ordering {
+    std::vector<int32_t> rank_cell_persistent;  // rank -> cell
+    std::vector<int32_t> rank_cell_plain;
+    // plain buckets: [rank_begin, rank_end) and whether they hold long pairs
+    struct Bucket {
+        int rank_begin, rank_end;
+        bool wave;
+    };
+    std::vector<Bucket> buckets;
+};
+
+int ceil_log2(int64_t x)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < x) ++b;
+    return b;
+}
+
+Ordering make_ordering(int R, int inter_max)
+{
+    struct Key {
+        int cell;
+        bool wave;
+        int bucket;
+        int64_t cost;
+        int s, c;
+    };
+    std::vector<Key> keys;
+    keys.reserve(kNumCells);
+    const int smax = (inter_max + R - 1) / R, cmax = (inter_max + 7) / 8;
+    for (int s = 1; s <= kMaxInterStrips; ++s)
+        for (int c = 1; c <= kMaxInterChunks; ++c) {
+            Key k;
+            k.cell = (s - 1) * kMaxInterChunks + (c - 1);
+            k.wave = false;
+            k.bucket = ceil_log2(std::max<int64_t>((int64_t)s * R, 8 * c));
+            const bool reachable = s <= smax && c <= cmax;
+            k.cost = reachable ? (int64_t)s * c : -1;
+            k.s = s;
+            k.c = c;
+            keys.push_back(k);
+        }
+    for (int b = 0; b < kNumLenBuckets; ++b)
+        for (int cb = 0; cb < kWaveCostBins; ++cb) {
+            Key k;
+            k.cell = kInterCells + b * kWaveCostBins + cb;
+            k.wave = true;
+            k.bucket = b;
+            k.cost = cb;
+            k.s = k.c = 0;
+            keys.push_back(k);
+        }
+    Ordering o;
+    // persistent: long pairs first, then short ones, each by decreasing cost
+    // (longest-processing-time-first order for the device work queue)
+    std::vector<Key> p = keys;
+    std::stable_sort(p.begin(), p.end(), [](const Key& x, const Key& y) {
+        if (x.wave != y.wave) return x.wave;
+        if (x.cost != y.cost) return x.cost > y.cost;
+        if (x.bucket != y.bucket) return x.bucket > y.bucket;
+        return x.s > y.s;
+    });
+    for (const Key& k : p) o.rank_cell_persistent.push_back(k.cell);
+    // plain: short-pair buckets by length, then long-pair buckets; inside a
+    // bucket by decreasing cost
+    std::vector<Key> q = keys;
+    std::stable_sort(q.begin(), q.end(), [](const Key& x, const Key& y) {
+        if (x.wave != y.wave) return !x.wave;
+        if (x.bucket != y.bucket) return x.bucket < y.bucket;
+        if (x.cost != y.cost) return x.cost > y.cost;
+        return x.s > y.s;
+    });
+    for (size_t r = 0; r < q.size(); ++r) {
+        o.rank_cell_plain.push_back(q[r].cell);
+        if (r == 0 || q[r].wave != q[r - 1].wave || q[r].bucket != q[r - 1].bucket)
+            o.buckets.push_back({(int)r, (int)r + 1, q[r].wave});
+        else
+            o.buckets.back().rank_end = (int)r + 1;
+    }
+    return o;
+}
+
+struct GraphKey {
+    const void* packed;
+    const void* offsets;
+    int64_t n_seqs;
+    const void* pairs;
+    int64_t n_pairs;
+    int32_t go, ge;
+    void* out;
+    int R, inter_max, grid;
+    bool operator<(const GraphKey& o) const
+    {
+        return std::tie(packed, offsets, n_seqs, pairs, n_pairs, go, ge, out, R, inter_max, grid) <
+               std::tie(o.packed, o.offsets, o.n_seqs, o.pairs, o.n_pairs, o.go, o.ge, o.out, o.R, o.inter_max,
+                        o.grid);
+    }
+};
+
+// Scratch and queues of one stream.  Kernels of two calls on the same stream
+// run in order, so they can share it; calls on different streams get their
+// own workspace.
+struct Workspace {
+    int64_t pair_cap = 0;
+    int32_t* pair_cell = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* cell_count = nullptr;
+    int32_t* rank_start = nullptr;
+    int32_t* counters = nullptr;
+    int64_t scratch_words = 0;
+    uint32_t* scratch = nullptr;
+    int32_t* host_rank_start = nullptr;  // pinned, plain form only
+    std::map<GraphKey, hipGraphExec_t> graphs;
+
+    ~Workspace()
+    {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        (void)hipFree(pair_cell);
+        (void)hipFree(perm);
+        (void)hipFree(cell_count);
+        (void)hipFree(rank_start);
+        (void)hipFree(counters);
+        (void)hipFree(scratch);
+        if (host_rank_start) (void)hipHostFree(host_rank_start);
+    }
+};
+
+struct Device {
+    bool ready = false;
+    int id = 0;
+    int n_cu = 0;
+    int R = 16;
+    int inter_max = 1024;
+    int bpc_user = 0;  // 0: occupancy-derived
+    Ordering ord;
+    int32_t* rank_cell_persistent = nullptr;
+    int32_t* rank_cell_plain = nullptr;
+    int32_t* err = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::map<hipStream_t, std::unique_ptr<Workspace>> ws;
+};
+
+std::mutex g_mutex;
+std::map<int, std::unique_ptr<Device>> g_devices;
+
+int upload_ordering(Device& d)
+{
+    d.ord = make_ordering(d.R, d.inter_max);
+    HIP_TRY(hipMemcpy(d.rank_cell_persistent, d.ord.rank_cell_persistent.data(), sizeof(int32_t) * kNumCells,
+                      hipMemcpyHostToDevice),
+            "upload ordering");
+    HIP_TRY(hipMemcpy(d.rank_cell_plain, d.ord.rank_cell_plain.data(), sizeof(int32_t) * kNumCells,
+                      hipMemcpyHostToDevice),
+            "upload ordering");
+    for (auto& w : d.ws) {  // graphs captured the old tables' contents by pointer only; still valid
+        (void)w;
+    }
+    return SW_OK;
+}
+
+int get_device(Device** out)
+{
+    int id = 0;
+    HIP_TRY(hipGetDevice(&id), "hipGetDevice");
+    auto& slot = g_devices[id];
+    if (!slot) slot.reset(new Device());
+    Device& d = *slot;
+    if (!d.ready) {
+        d.id = id;
+        HIP_TRY(hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, id), "device attributes");
+        HIP_TRY(set_kernel_attributes(), "kernel attributes");
+        HIP_TRY(hipMalloc(&d.rank_cell_persistent, sizeof(int32_t) * kNumCells), "hipMalloc");
+        HIP_TRY(hipMalloc(&d.rank_cell_plain, sizeof(int32_t) * kNumCells), "hipMalloc");
+        HIP_TRY(hipMalloc(&d.err, sizeof(int32_t)), "hipMalloc");
+        HIP_TRY(hipMemset(d.err, 0, sizeof(int32_t)), "hipMemset");
+        HIP_TRY(hipStreamCreateWithFlags(&d.capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+        int rc = upload_ordering(d);
+        if (rc != SW_OK) return rc;
+        d.ready = true;
+    }
+    *out = &d;
+    return SW_OK;
+}
+
+int blocks_per_cu(const Device& d)
+{
+    if (d.bpc_user > 0) return d.bpc_user;
+    int lds_per_cu = 0;
+    if (hipDeviceGetAttribute(&lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, d.id) !=
+            hipSuccess ||
+        lds_per_cu <= 0)
+        lds_per_cu = 64 * 1024;
+    int b = lds_per_cu / (int)lds_bytes(d.R);
+    return std::max(1, std::min(b, 8));
+}
+
+template <typename T>
+int grow(T** p, int64_t count)
+{
+    (void)hipFree(*p);
+    *p = nullptr;
+    HIP_TRY(hipMalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(count, 1)), "hipMalloc workspace");
+    return SW_OK;
+}
+
+int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, int grid, Workspace** out)
+{
+    auto& slot = d.ws[stream];
+    if (!slot) slot.reset(new Workspace());
+    Workspace& w = *slot;
+    bool changed = false;
+    if (!w.cell_count) {
+        int rc;
+        if ((rc = grow(&w.cell_count, kNumCells)) || (rc = grow(&w.rank_start, kNumCells + 1)) ||
+            (rc = grow(&w.counters, kNumCounters)))
+            return rc;
+        HIP_TRY(hipHostMalloc((void**)&w.host_rank_start, sizeof(int32_t) * (kNumCells + 1)), "hipHostMalloc");
+        changed = true;
+    }
+    if (n_pairs > w.pair_cap) {
+        const int64_t cap = std::max<int64_t>(n_pairs, 2 * w.pair_cap);
+        int rc;
+        if ((rc = grow(&w.pair_cell, cap)) || (rc = grow(&w.perm, cap))) return rc;
+        w.pair_cap = cap;
+        changed = true;
+    }
+    const int64_t need = (int64_t)grid * slot_words(d.R, d.inter_max);
+    if (need > w.scratch_words) {
+        int rc = grow(&w.scratch, need);
+        if (rc) return rc;
+        w.scratch_words = need;
+        changed = true;
+    }
+    if (changed) {
+        for (auto& g : w.graphs) (void)hipGraphExecDestroy(g.second);
+        w.graphs.clear();
+    }
+    *out = &w;
+    return SW_OK;
+}
+
+int read_and_clear_errors(Device& d, hipStream_t stream)
+{
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    int32_t bits = 0;
+    HIP_TRY(hipMemcpy(&bits, d.err, sizeof(bits), hipMemcpyDeviceToHost), "read errors");
+    if (bits) HIP_TRY(hipMemset(d.err, 0, sizeof(int32_t)), "clear errors");
+    if (bits & kErrInternal) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "internal consistency check failed on the device");
+        return SW_EDEVICE;
+    }
+    if (bits & kErrRange) return SW_ERANGE;
+    if (bits & kErrCode) return SW_ECODE;
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sw_packed_bytes(int64_t n_residues)
+{
+    if (n_residues < 0) return 0;
+    return packed_bytes(n_residues);
+}
+
+int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, size_t packed_cap, void* stream)
+{
+    if (!packed_dev || n_residues < 0 || (n_residues > 0 && !ascii_dev)) return SW_EINVAL;
+    if (packed_cap < packed_bytes(n_residues)) return SW_ENOMEM;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* d = nullptr;
+    int rc = get_device(&d);
+    if (rc) return rc;
+    HIP_TRY(launch_pack(ascii_dev, n_residues, packed_dev, d->err, (hipStream_t)stream), "pack launch");
+    return SW_OK;
+}
+
+int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs, const int32_t* pairs_dev,
+                   int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream_, uint32_t flags)
+{
+    if (!scoring || n_pairs < 0 || n_seqs < 0) return SW_EINVAL;
+    if (flags & ~(SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH)) return SW_EINVAL;
+    if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
+        scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
+        return SW_EINVAL;
+    if (n_pairs == 0) return SW_OK;
+    if (!packed_dev || !offsets_dev || !pairs_dev || !out_dev) return SW_EINVAL;
+    if (n_pairs > (int64_t)0x7FFFFFFF - 64 || n_seqs > (int64_t)0x7FFFFFFF) return SW_ERANGE;
+    hipStream_t stream = (hipStream_t)stream_;
+
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* dp = nullptr;
+    int rc = get_device(&dp);
+    if (rc) return rc;
+    Device& d = *dp;
+    const int grid = d.n_cu * blocks_per_cu(d);
+    Workspace* wp = nullptr;
+    if ((rc = get_workspace(d, stream, n_pairs, grid, &wp))) return rc;
+    Workspace& w = *wp;
+
+    Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.blk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(packed_dev) + kHeaderBytes);
+    a.hdr = reinterpret_cast<const PackedHeader*>(packed_dev);
+    a.offsets = offsets_dev;
+    a.n_seqs = n_seqs;
+    a.pairs = pairs_dev;
+    a.n_pairs = n_pairs;
+    a.out = out_dev;
+    a.pair_cell = w.pair_cell;
+    a.perm = w.perm;
+    a.cell_count = w.cell_count;
+    a.rank_start = w.rank_start;
+    a.counters = w.counters;
+    a.err = d.err;
+    a.scratch = w.scratch;
+    a.slot_words = slot_words(d.R, d.inter_max);
+    a.go = scoring->gap_open;
+    a.ge = scoring->gap_extend;
+    a.rows_per_lane = d.R;
+    a.inter_max_len = d.inter_max;
+
+    if (flags & SW_PLAIN) {
+        a.rank_cell = d.rank_cell_plain;
+        HIP_TRY(launch_prepare(a, stream), "prepare launch");
+        HIP_TRY(hipMemcpyAsync(w.host_rank_start, w.rank_start, sizeof(int32_t) * (kNumCells + 1),
+                               hipMemcpyDeviceToHost, stream),
+                "bucket sizes");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        for (const auto& b : d.ord.buckets) {
+            const int first = w.host_rank_start[b.rank_begin];
+            const int count = w.host_rank_start[b.rank_end] - first;
+            if (count <= 0) continue;
+            const int items = b.wave ? count : (count + kWave - 1) / kWave;
+            HIP_TRY(launch_plain(a, b.wave, first, count, std::min(items, grid), stream), "plain launch");
+        }
+    } else {
+        a.rank_cell = d.rank_cell_persistent;
+        if (flags & SW_NO_GRAPH) {
+            HIP_TRY(launch_prepare(a, stream), "prepare launch");
+            HIP_TRY(launch_persistent(a, grid, stream), "persistent launch");
+        } else {
+            GraphKey key{packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, a.go, a.ge, out_dev,
+                         d.R, d.inter_max, grid};
+            auto it = w.graphs.find(key);
+            if (it == w.graphs.end()) {
+                if (w.graphs.size() >= 16) {
+                    (void)hipGraphExecDestroy(w.graphs.begin()->second);
+                    w.graphs.erase(w.graphs.begin());
+                }
+                hipGraph_t g = nullptr;
+                HIP_TRY(hipStreamBeginCapture(d.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+                hipError_t e1 = launch_prepare(a, d.capture_stream);
+                hipError_t e2 = e1 == hipSuccess ? launch_persistent(a, grid, d.capture_stream) : e1;
+                hipError_t e3 = hipStreamEndCapture(d.capture_stream, &g);
+                if (e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return dev_error(e2, "capture launch");
+                }
+                HIP_TRY(e3, "end capture");
+                hipGraphExec_t ex = nullptr;
+                hipError_t e4 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                HIP_TRY(e4, "graph instantiate");
+                it = w.graphs.emplace(key, ex).first;
+            }
+            HIP_TRY(hipGraphLaunch(it->second, stream), "graph launch");
+        }
+    }
+    if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
+    return SW_OK;
+}
+
+int sw_check(void* stream)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* d = nullptr;
+    int rc = get_device(&d);
+    if (rc) return rc;
+    return read_and_clear_errors(*d, (hipStream_t)stream);
+}
+
+int sw_set_tuning(const sw_tuning* t)
+{
+    if (!t) return SW_EINVAL;
+    if (t->rows_per_lane > 0 && t->rows_per_lane != 16 && t->rows_per_lane != 32) return SW_EINVAL;
+    if (t->inter_max_len > 0 && (t->inter_max_len < 64 || t->inter_max_len > kMaxInterLen)) return SW_EINVAL;
+    if (t->blocks_per_cu > 8) return SW_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* d = nullptr;
+    int rc = get_device(&d);
+    if (rc) return rc;
+    const int R = t->rows_per_lane > 0 ? t->rows_per_lane : d->R;
+    const int im = t->inter_max_len > 0 ? t->inter_max_len : d->inter_max;
+    if ((im + R - 1) / R > kMaxInterStrips) return SW_EINVAL;
+    const bool reorder = R != d->R || im != d->inter_max;
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    d->R = R;
+    d->inter_max = im;
+    if (t->blocks_per_cu > 0) d->bpc_user = t->blocks_per_cu;
+    if (reorder) {
+        rc = upload_ordering(*d);
+        if (rc) return rc;
+    }
+    for (auto& w : d->ws) {  // graphs bake in the kernel shape
+        for (auto& g : w.second->graphs) (void)hipGraphExecDestroy(g.second);
+        w.second->graphs.clear();
+    }
+    return SW_OK;
+}
+
+int sw_get_tuning(sw_tuning* t)
+{
+    if (!t) return SW_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* d = nullptr;
+    int rc = get_device(&d);
+    if (rc) return rc;
+    t->rows_per_lane = d->R;
+    t->inter_max_len = d->inter_max;
+    t->blocks_per_cu = blocks_per_cu(*d);
+    return SW_OK;
+}
+
+int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters)
+{
+    if (matrix_id != 0 || !scores || !letters) return SW_EINVAL;
+    matrix_ncbi(scores, letters);
+    return SW_OK;
+}
+
+const char* sw_strerror(int status)
+{
+    switch (status) {
+    case SW_OK: return "ok";
+    case SW_EINVAL: return "invalid argument";
+    case SW_ERANGE: return "pair index or sequence length out of range";
+    case SW_ECODE: return "residue outside the alphabet";
+    case SW_ENOMEM: return "out of memory or buffer too small";
+    case SW_EDEVICE: return "HIP runtime error";
+    case SW_ETIMEOUT: return "timed out";
+    case SW_EAGAIN: return "not admissible now";
+    case SW_ECANCELED: return "canceled";
+    default: return "unknown status";
+    }
+}
+
+const char* sw_last_device_error(void) { return g_last_error; }
+
+}  // extern "C"

@@ -1,0 +1,914 @@
+// Device code of the batched Smith-Waterman library, written for gfx950.
+//
+// What is computed per pair (query q of length m, reference r of length n):
+// the local-alignment recurrence with affine gaps over the whole m x n matrix
+// (the paper, section "Load balancing techniques": the aligner fills the
+// entire matrix, so a pair costs m*n), the best score S, the first cell of S
+// in (query, reference) lexicographic order, and the start found by running
+// the same recurrence over the reversed prefixes (first reversed cell that
+// reaches S).  All arithmetic is exact int32.
+//
+// Cell update used everywhere (8-9 VALU instructions per cell):
+//   d  = H[i-1][j-1] + s(q_i, r_j)           one SDWA add (profile byte, sign-extended)
+//   H  = max3(d, E[i][j], F[i][j])           E, F >= 0, so H >= 0 is the local floor
+//   hg = sat(H - go)                         v_sub_u32 clamp
+//   E[i][j+1] = max(E[i][j] - ge, hg)        hg >= 0 keeps E >= 0
+//   F[i+1][j] = max(F[i][j] - ge, hg)
+//   K[r] = max(K[r], H << TB | tag(j))       per-row best with the earliest column
+// Keeping E and F saturated at 0 leaves H exactly as in the textbook
+// recurrence: by induction E_sat = max(E, 0), and H only uses max(0, E).
+//
+// Two kernel bodies:
+//  * lane-per-pair ("inter"): each lane aligns its own pair; the lane keeps R
+//    query rows in registers and sweeps the reference; horizontal strips of R
+//    rows hand their bottom row to the next strip through a per-block scratch
+//    slot; the substitution scores come from a per-lane query profile in LDS.
+//  * wave-per-pair ("wavefront"): the 64 lanes of a wave split a 64R-row strip,
+//    lane l owning rows [lR, lR+R); at step t lane l computes column t - l, and
+//    the bottom H and F of lane l-1 (its previous step) arrive by DPP
+//    wave_shr:1.  Strips hand over their bottom row through the scratch slot.
+
+#include <algorithm>
+
+#include "sw_internal.h"
+
+namespace swk {
+
+// ------------------------------------------------------------------ alphabet
+// The library's own copy of BLOSUM62 (NCBI symbol order) and its symbol order
+// for packing: the 16 most frequent amino acids get codes 0..15 so that their
+// high bit is 0.
+static constexpr char kNcbiOrder[kNumSym + 1] = "ARNDCQEGHILKMFPSTWYVBZX*";
+static constexpr char kCodeOrder[kNumSym + 1] = "LAGVIKSEDRTFNPQYHMCWBZX*";
+static constexpr int8_t kBlosum62Ncbi[kNumSym][kNumSym] = {
+    // A   R   N   D   C   Q   E   G   H   I   L   K   M   F   P   S   T   W   Y   V   B   Z   X   *
+    { 4, -1, -2, -2,  0, -1, -1,  0, -2, -1, -1, -1, -1, -2, -1,  1,  0, -3, -2,  0, -2, -1,  0, -4},  // A
+    {-1,  5,  0, -2, -3,  1,  0, -2,  0, -3, -2,  2, -1, -3, -2, -1, -1, -3, -2, -3, -1,  0, -1, -4},  // R
+    {-2,  0,  6,  1, -3,  0,  0,  0,  1, -3, -3,  0, -2, -3, -2,  1,  0, -4, -2, -3,  3,  0, -1, -4},  // N
+    {-2, -2,  1,  6, -3,  0,  2, -1, -1, -3, -4, -1, -3, -3, -1,  0, -1, -4, -3, -3,  4,  1, -1, -4},  // D
+    { 0, -3, -3, -3,  9, -3, -4, -3, -3, -1, -1, -3, -1, -2, -3, -1, -1, -2, -2, -1, -3, -3, -2, -4},  // C
+    {-1,  1,  0,  0, -3,  5,  2, -2,  0, -3, -2,  1,  0, -3, -1,  0, -1, -2, -1, -2,  0,  3, -1, -4},  // Q
+    {-1,  0,  0,  2, -4,  2,  5, -2,  0, -3, -3,  1, -2, -3, -1,  0, -1, -3, -2, -2,  1,  4, -1, -4},  // E
+    { 0, -2,  0, -1, -3, -2, -2,  6, -2, -4, -4, -2, -3, -3, -2,  0, -2, -2, -3, -3, -1, -2, -1, -4},  // G
+    {-2,  0,  1, -1, -3,  0,  0, -2,  8, -3, -3, -1, -2, -1, -2, -1, -2, -2,  2, -3,  0,  0, -1, -4},  // H
+    {-1, -3, -3, -3, -1, -3, -3, -4, -3,  4,  2, -3,  1,  0, -3, -2, -1, -3, -1,  3, -3, -3, -1, -4},  // I
+    {-1, -2, -3, -4, -1, -2, -3, -4, -3,  2,  4, -2,  2,  0, -3, -2, -1, -2, -1,  1, -4, -3, -1, -4},  // L
+    {-1,  2,  0, -1, -3,  1,  1, -2, -1, -3, -2,  5, -1, -3, -1,  0, -1, -3, -2, -2,  0,  1, -1, -4},  // K
+    {-1, -1, -2, -3, -1,  0, -2, -3, -2,  1,  2, -1,  5,  0, -2, -1, -1, -1, -1,  1, -3, -1, -1, -4},  // M
+    {-2, -3, -3, -3, -2, -3, -3, -3, -1,  0,  0, -3,  0,  6, -4, -2, -2,  1,  3, -1, -3, -3, -1, -4},  // F
+    {-1, -2, -2, -1, -3, -1, -1, -2, -2, -3, -3, -1, -2, -4,  7, -1, -1, -4, -3, -2, -2, -1, -2, -4},  // P
+    { 1, -1,  1,  0, -1,  0,  0,  0, -1, -2, -2,  0, -1, -2, -1,  4,  1, -3, -2, -2,  0,  0,  0, -4},  // S
+    { 0, -1,  0, -1, -1, -1, -1, -2, -2, -1, -1, -1, -1, -2, -1,  1,  5, -2, -2,  0, -1, -1,  0, -4},  // T
+    {-3, -3, -4, -4, -2, -2, -3, -2, -2, -3, -2, -3, -1,  1, -4, -3, -2, 11,  2, -3, -4, -3, -2, -4},  // W
+    {-2, -2, -2, -3, -2, -1, -2, -3,  2, -1, -1, -2, -1,  3, -3, -2, -2,  2,  7, -1, -3, -2, -1, -4},  // Y
+    { 0, -3, -3, -3, -1, -2, -2, -3, -3,  3,  1, -2,  1, -1, -2, -2,  0, -3, -1,  4, -3, -2, -1, -4},  // V
+    {-2, -1,  3,  4, -3,  0,  1, -1,  0, -3, -4,  0, -3, -3, -2,  0, -1, -4, -3, -3,  4,  1, -1, -4},  // B
+    {-1,  0,  0,  1, -3,  3,  4, -2,  0, -3, -3,  1, -1, -3, -1,  0, -1, -3, -2, -2,  1,  4, -1, -4},  // Z
+    { 0, -1, -1, -1, -2, -1, -1, -1, -1, -1, -1, -1, -1, -1, -2,  0,  0, -2, -1, -1, -1, -1, -1, -4},  // X
+    {-4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4,  1},  // *
+};
+
+static constexpr int ncbi_index(char c)
+{
+    for (int k = 0; k < kNumSym; ++k)
+        if (kNcbiOrder[k] == c) return k;
+    return -1;
+}
+
+struct CodeTables {
+    uint32_t tab[kNumCodes][8];  // row c: bytes s(c, x) for x = 0..31 (pad and unused: -128)
+    uint8_t ascii[256];          // ASCII -> code, 0xFF if not a symbol
+};
+
+static constexpr CodeTables make_tables()
+{
+    CodeTables t{};
+    for (int a = 0; a < kNumCodes; ++a)
+        for (int w = 0; w < 8; ++w) {
+            uint32_t word = 0;
+            for (int k = 0; k < 4; ++k) {
+                int b = 4 * w + k;
+                int v = -128;
+                if (a < kNumSym && b < kNumSym)
+                    v = kBlosum62Ncbi[ncbi_index(kCodeOrder[a])][ncbi_index(kCodeOrder[b])];
+                word |= (uint32_t)(uint8_t)(int8_t)v << (8 * k);
+            }
+            t.tab[a][w] = word;
+        }
+    for (int c = 0; c < 256; ++c) t.ascii[c] = 0xFF;
+    for (int a = 0; a < kNumSym; ++a) t.ascii[(unsigned char)kCodeOrder[a]] = (uint8_t)a;
+    return t;
+}
+
+static constexpr CodeTables kTables = make_tables();
+__constant__ CodeTables c_tables = kTables;
+
+void matrix_ncbi(int8_t out[kNumSym * kNumSym], char letters[kNumSym + 1])
+{
+    for (int a = 0; a < kNumSym; ++a)
+        for (int b = 0; b < kNumSym; ++b) out[a * kNumSym + b] = kBlosum62Ncbi[a][b];
+    for (int a = 0; a <= kNumSym; ++a) letters[a] = kNcbiOrder[a];
+}
+
+const char* code_order() { return kCodeOrder; }
+
+// ------------------------------------------------------------------ packed residues
+// Word of the nibble / high plane holding residue p (p may be as low as
+// -kGuardRes).  Planes are interleaved in 256-residue blocks of 40 words.
+__device__ __forceinline__ int64_t nib_word(int64_t p)
+{
+    int64_t q = p + kGuardRes;
+    return (q >> 8) * 40 + ((q >> 3) & 31);
+}
+__device__ __forceinline__ int64_t hib_word(int64_t p)
+{
+    int64_t q = p + kGuardRes;
+    return (q >> 8) * 40 + 32 + ((q >> 5) & 7);
+}
+
+// A sequence view: residues B + x for x >= -256 addressed with 32-bit offsets
+// from the block before the one holding B.
+struct SeqView {
+    const uint32_t* ptr;
+    int off;
+};
+
+__device__ __forceinline__ SeqView seq_view(const uint32_t* __restrict__ blk, int64_t B)
+{
+    const int64_t q = B + kGuardRes;
+    SeqView v;
+    v.ptr = blk + ((q >> 8) - 1) * 40;
+    v.off = (int)(q & 255) + 256;
+    return v;
+}
+
+__device__ __forceinline__ int view_nib(int q) { return (q >> 8) * 40 + ((q >> 3) & 31); }
+__device__ __forceinline__ int view_hib(int q) { return (q >> 8) * 40 + 32 + ((q >> 5) & 7); }
+
+// Codes of the 8 residues B+x .. B+x+7: nibble k of nw, bit k of hw.
+__device__ __forceinline__ void window8(const SeqView& v, int x, uint32_t& nw, uint32_t& hw)
+{
+    const int q = v.off + x;
+    const uint32_t a0 = v.ptr[view_nib(q)], a1 = v.ptr[view_nib(q + 8)];
+    nw = __builtin_amdgcn_alignbit(a1, a0, (uint32_t)(q & 7) * 4u);
+    const uint32_t b0 = v.ptr[view_hib(q)], b1 = v.ptr[view_hib(q + 32)];
+    hw = __builtin_amdgcn_alignbit(b1, b0, (uint32_t)(q & 31));
+}
+
+// Code of the single residue B + x.
+__device__ __forceinline__ uint32_t code_at(const SeqView& v, int x)
+{
+    const int q = v.off + x;
+    return ((v.ptr[view_nib(q)] >> ((q & 7) * 4)) & 15u) | (((v.ptr[view_hib(q)] >> (q & 31)) & 1u) << 4);
+}
+
+// Codes of R consecutive rows starting at `row0`, read forwards from the view
+// base (REV: backwards).  Rows >= M get the pad code.
+template <int R, bool REV>
+__device__ __forceinline__ void row_codes(const SeqView& qv, int row0, int M, uint32_t (&qc)[R])
+{
+    const bool any = row0 < M;
+    const int x = !any ? 0 : (REV ? -row0 - (R - 1) : row0);
+#pragma unroll
+    for (int k8 = 0; k8 < R / 8; ++k8) {
+        uint32_t nw, hw;
+        window8(qv, x + 8 * k8, nw, hw);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int idx = 8 * k8 + k;                 // window position
+            const int r = REV ? (R - 1 - idx) : idx;    // row within the strip
+            const uint32_t c = ((nw >> (4 * k)) & 15u) | (((hw >> k) & 1u) << 4);
+            qc[r] = (row0 + r < M) ? c : (uint32_t)kPadCode;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ query profile in LDS
+// Layout [code][lane][R bytes]: lane l's scores for its R rows against a
+// reference residue `code` are 16 or 32 contiguous bytes; a wave's reads of
+// one row of the layout are contiguous in lane order, so ds_read_b128 is
+// conflict-free whatever codes the lanes hold.
+template <int R>
+__device__ __forceinline__ void build_profile(uint8_t* prof, int lane, const uint32_t (&qc)[R])
+{
+    uint32_t sel[R / 4][3];
+#pragma unroll
+    for (int w = 0; w < R / 4; ++w) {
+        uint32_t s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t c = qc[4 * w + i];
+            const uint32_t g = c >> 3, idx = c & 7u;
+            s0 |= (g == 0 ? idx : 12u) << (8 * i);   // selector 12 -> byte 0x00
+            s1 |= (g == 1 ? idx : 12u) << (8 * i);
+            s2 |= (g == 2 ? idx : 12u) << (8 * i);
+        }
+        sel[w][0] = s0;
+        sel[w][1] = s1;
+        sel[w][2] = s2;
+    }
+    uint8_t* base = prof + lane * R;
+    for (int c = 0; c < kNumSym; ++c) {
+        const uint32_t* t = c_tables.tab[c];
+        const uint32_t t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3], t4 = t[4], t5 = t[5];
+        uint32_t v[R / 4];
+#pragma unroll
+        for (int w = 0; w < R / 4; ++w)
+            v[w] = __builtin_amdgcn_perm(t1, t0, sel[w][0]) | __builtin_amdgcn_perm(t3, t2, sel[w][1]) |
+                   __builtin_amdgcn_perm(t5, t4, sel[w][2]);
+        uint4* dst = reinterpret_cast<uint4*>(base + c * (kWave * R));
+#pragma unroll
+        for (int w = 0; w < R / 16; ++w) dst[w] = make_uint4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+    }
+    uint4* dst = reinterpret_cast<uint4*>(base + kPadCode * (kWave * R));
+#pragma unroll
+    for (int w = 0; w < R / 16; ++w) dst[w] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+}
+
+template <int R>
+__device__ __forceinline__ void load_profile(const uint8_t* prof_lane, uint32_t code, uint32_t (&w)[R / 4])
+{
+    const uint4* p = reinterpret_cast<const uint4*>(prof_lane + code * (uint32_t)(kWave * R));
+#pragma unroll
+    for (int k = 0; k < R / 16; ++k) {
+        const uint4 v = p[k];
+        w[4 * k] = v.x;
+        w[4 * k + 1] = v.y;
+        w[4 * k + 2] = v.z;
+        w[4 * k + 3] = v.w;
+    }
+}
+
+// ------------------------------------------------------------------ the cell update
+// h + sign_extend(byte SEL of w), one v_add_u32 with an SDWA byte operand.
+template <int SEL>
+__device__ __forceinline__ int add_sbyte(int h, uint32_t w)
+{
+    int d;
+    if constexpr (SEL == 0)
+        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+            : "=v"(d) : "v"(h), "v"(w));
+    else if constexpr (SEL == 1)
+        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+            : "=v"(d) : "v"(h), "v"(w));
+    else if constexpr (SEL == 2)
+        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+            : "=v"(d) : "v"(h), "v"(w));
+    else
+        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+            : "=v"(d) : "v"(h), "v"(w));
+    return d;
+}
+
+template <int R, int I>
+struct RowUnroll {
+    template <int TB>
+    static __device__ __forceinline__ void run(int (&H)[R], int (&E)[R], uint32_t (&K)[R],
+                                               const uint32_t (&w)[R / 4], int& d, int& F,
+                                               uint32_t tag, uint32_t go, int ge)
+    {
+        int dn = 0;
+        if constexpr (I + 1 < R) dn = add_sbyte<(I + 1) & 3>(H[I], w[(I + 1) >> 2]);
+        const int h = max(max(d, E[I]), F);
+        H[I] = h;
+        const int hg = (int)__builtin_elementwise_sub_sat((uint32_t)h, go);
+        E[I] = max(E[I] - ge, hg);
+        F = max(F - ge, hg);
+        K[I] = max(K[I], ((uint32_t)h << TB) | tag);
+        d = dn;
+        if constexpr (I + 1 < R) RowUnroll<R, I + 1>::template run<TB>(H, E, K, w, d, F, tag, go, ge);
+    }
+};
+
+// One column of a lane's R rows.  hdiag = H[row0-1][j-1]; F enters as
+// F[row0][j] and leaves as F[row0+R][j].
+template <int R, int TB>
+__device__ __forceinline__ void column_step(int (&H)[R], int (&E)[R], uint32_t (&K)[R],
+                                            const uint32_t (&w)[R / 4], int hdiag, int& F,
+                                            uint32_t tag, uint32_t go, int ge)
+{
+    int d = add_sbyte<0>(hdiag, w[0]);
+    RowUnroll<R, 0>::template run<TB>(H, E, K, w, d, F, tag, go, ge);
+}
+
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int old, int src)
+{
+    return __builtin_amdgcn_update_dpp(old, src, CTRL, 0xF, 0xF, false);
+}
+constexpr int kWaveShr1 = 0x138;  // lane l <- lane l-1; lane 0 keeps `old`
+constexpr int kWaveShl1 = 0x130;  // lane l <- lane l+1; lane 63 keeps `old`
+
+__device__ __forceinline__ void block_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+struct Best {
+    int s, i, j;
+};
+
+// ------------------------------------------------------------------ lane-per-pair sweep
+// Each lane aligns rows [0, M) x columns [0, N) of its own pair.  Row i reads
+// query position Q0 + i (REV: Q0 - i), column j reads reference position
+// R0 + j (REV: R0 - j).  Forward: returns the best score and its first cell.
+// REV: stops a lane after the first strip whose rows reach `target`.
+// Scratch slot layout: [chunk][lane][8 columns] of (H | F << 16).
+template <int R, bool REV>
+__device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__ slot, int64_t Q0, int M,
+                            int64_t R0, int N, int target)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint8_t* prof_lane = prof + lane * R;
+    const uint32_t go = (uint32_t)a.go;
+    const int ge = a.ge;
+    Best b{0, -1, -1};
+    const int my_strips = (M > 0 && N > 0) ? (M + R - 1) / R : 0;
+    const int my_chunks = (N + 7) / 8;
+    const int ws = uni(wave_max(my_strips));
+    const int wc = uni(wave_max(my_strips > 0 ? my_chunks : 0));
+    bool done = my_strips == 0 || (REV && target <= 0);
+    const SeqView qv = seq_view(a.blk, Q0);
+    const SeqView rv = seq_view(a.blk, R0);
+    uint4* slot4 = reinterpret_cast<uint4*>(slot) + 2 * lane;
+
+    for (int s = 0; s < ws; ++s) {
+        if (__ballot(!done && s < my_strips) == 0) break;
+        const bool act = !done && s < my_strips;
+        const int row0 = s * R;
+        {
+            uint32_t qc[R];
+            row_codes<R, REV>(qv, act ? row0 : M, M, qc);
+            build_profile<R>(prof, lane, qc);
+        }
+        int H[R], E[R];
+        uint32_t K[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            H[r] = 0;
+            E[r] = 0;
+            K[r] = 0;
+        }
+        int hdiag = 0;
+        const bool read_top = s > 0;  // uniform
+
+        // chunk c covers columns 8c .. 8c+7; a lane past its last column reads
+        // position 0 and masks everything to the pad code
+        auto chunk_x = [&](int c) -> int { return 8 * c >= N ? 0 : (REV ? -8 * c - 7 : 8 * c); };
+        uint32_t nw_n, hw_n;
+        window8(rv, chunk_x(0), nw_n, hw_n);
+        uint4 t0_n = make_uint4(0, 0, 0, 0), t1_n = make_uint4(0, 0, 0, 0);
+        if (read_top) {
+            t0_n = slot4[0];
+            t1_n = slot4[1];
+        }
+        for (int c = 0; c < wc; ++c) {
+            uint32_t nw = nw_n, hw = hw_n;
+            const uint4 t0 = t0_n, t1 = t1_n;
+            const int cn = min(c + 1, wc - 1);
+            window8(rv, chunk_x(cn), nw_n, hw_n);
+            if (read_top) {
+                t0_n = slot4[cn * 2 * kWave];
+                t1_n = slot4[cn * 2 * kWave + 1];
+            }
+            const int valid = min(max(N - 8 * c, 0), 8);
+            if (valid < 8) {
+                if (REV) {
+                    const uint32_t m4 = valid == 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu >> (4 * valid));
+                    nw = (nw & ~m4) | (0x88888888u & m4);
+                    hw |= 0xFFu >> valid;
+                } else {
+                    const uint32_t m4 = valid == 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (4 * valid));
+                    nw = (nw & ~m4) | (0x88888888u & m4);
+                    hw |= (0xFFu << valid) & 0xFFu;
+                }
+            }
+            const uint32_t top[8] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+            uint32_t bot[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int nb = REV ? 7 - k : k;
+                const uint32_t code = ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
+                uint32_t w[R / 4];
+                load_profile<R>(prof_lane, code, w);
+                const int htop = (int)(top[k] & 0xFFFFu);
+                int F = (int)(top[k] >> 16);
+                const uint32_t tag = (uint32_t)uni(0xFFFF - (8 * c + k));
+                column_step<R, 16>(H, E, K, w, hdiag, F, tag, go, ge);
+                hdiag = htop;
+                bot[k] = (uint32_t)H[R - 1] | ((uint32_t)F << 16);
+            }
+            // every lane writes its own slot region; a lane without a next
+            // strip never reads it back before overwriting it
+            slot4[c * 2 * kWave] = make_uint4(bot[0], bot[1], bot[2], bot[3]);
+            slot4[c * 2 * kWave + 1] = make_uint4(bot[4], bot[5], bot[6], bot[7]);
+        }
+        block_fence();
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int sc = (int)(K[r] >> 16);
+                if (row0 + r < M && sc > b.s) {
+                    b.s = sc;
+                    b.i = row0 + r;
+                    b.j = (int)(0xFFFFu - (K[r] & 0xFFFFu));
+                }
+            }
+            if (REV && b.s >= target) done = true;
+        }
+    }
+    return b;
+}
+
+// ------------------------------------------------------------------ wave-per-pair sweep
+// One pair per wave.  Strip s covers rows [64Rs, 64R(s+1)); lane l owns rows
+// 64Rs + lR + [0, R).  Scratch slot: int2 (H, F) per column, the bottom row of
+// the previous strip.  Tags cover 4096 steps; trackers are folded into
+// (score, step) per row every 4096 steps.
+template <int R, bool REV>
+__device__ Best wave_sweep(const Args& a, uint8_t* prof, int2* __restrict__ slot, int64_t Q0, int M,
+                           int64_t R0, int N, int target)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    Q0 = uni64(Q0);
+    R0 = uni64(R0);
+    M = uni(M);
+    N = uni(N);
+    target = uni(target);
+    const uint8_t* prof_lane = prof + lane * R;
+    const uint32_t go = (uint32_t)a.go;
+    const int ge = a.ge;
+    Best b{0, -1, -1};
+    if (M <= 0 || N <= 0 || (REV && target <= 0)) return b;
+    constexpr int kRowsPerStrip = kWave * R;
+    const int nstrips = (M + kRowsPerStrip - 1) / kRowsPerStrip;
+    const SeqView qv = seq_view(a.blk, Q0);
+    const SeqView rv = seq_view(a.blk, R0);
+
+    for (int s = 0; s < nstrips; ++s) {
+        const int rows_left = M - s * kRowsPerStrip;
+        const int L = min(kWave, (rows_left + R - 1) / R);  // lanes holding at least one row
+        const int row0 = s * kRowsPerStrip + lane * R;
+        {
+            uint32_t qc[R];
+            row_codes<R, REV>(qv, row0, M, qc);
+            build_profile<R>(prof, lane, qc);
+        }
+        int H[R], E[R];
+        uint32_t K[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            H[r] = 0;
+            E[r] = 0;
+            K[r] = 0;
+        }
+        // this lane's best (score desc, row asc, column asc) over folded blocks
+        int ls = 0, li = -1, lj = -1;
+        int hdiag = 0, hbot = 0, fbel = 0;
+        int ccode = kPadCode;
+        int in_code = kPadCode, in_h = 0, in_f = 0;  // lane k: column t + k of this 64-step block
+        int out_h = 0, out_f = 0;                    // lane k: bottom of column cb - 63 + k
+        const bool read_top = s > 0;
+        const bool write_bot = s + 1 < nstrips;      // then L == 64
+        const int T = N + L - 1;
+        // Fold the 4096-step trackers: a row's earlier block wins ties (strict
+        // '>'), a smaller row wins ties against a larger one.
+        auto fold = [&](int tbase) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int sc = (int)(K[r] >> 12);
+                const int row = row0 + r;
+                if (row < M && sc > 0 && (sc > ls || (sc == ls && row < li))) {
+                    ls = sc;
+                    li = row;
+                    lj = tbase + 4095 - (int)(K[r] & 4095u) - lane;
+                }
+                K[r] = 0;
+            }
+        };
+        for (int t = 0; t < T; ++t) {
+            if ((t & 63) == 0) {
+                const int col = t + lane;
+                in_code = col < N ? (int)code_at(rv, REV ? -col : col) : kPadCode;
+                if (read_top && col < N) {
+                    const int2 v = slot[col];
+                    in_h = v.x;
+                    in_f = v.y;
+                } else {
+                    in_h = 0;
+                    in_f = 0;
+                }
+            }
+            ccode = dpp_mov<kWaveShr1>(in_code, ccode);
+            const int htop = dpp_mov<kWaveShr1>(in_h, hbot);
+            const int ftop = dpp_mov<kWaveShr1>(in_f, fbel);
+            in_code = dpp_mov<kWaveShl1>(in_code, in_code);
+            in_h = dpp_mov<kWaveShl1>(in_h, in_h);
+            in_f = dpp_mov<kWaveShl1>(in_f, in_f);
+            const int j = t - lane;
+            if (j >= 0 && j < N && lane < L) {
+                uint32_t w[R / 4];
+                load_profile<R>(prof_lane, (uint32_t)ccode, w);
+                int F = ftop;
+                column_step<R, 12>(H, E, K, w, hdiag, F, (uint32_t)uni(4095 - (t & 4095)), go, ge);
+                hdiag = htop;
+                hbot = H[R - 1];
+                fbel = F;
+            }
+            if (write_bot) {
+                const int cb = t - (kWave - 1);  // column finished by lane 63 at this step
+                out_h = dpp_mov<kWaveShl1>(hbot, out_h);
+                out_f = dpp_mov<kWaveShl1>(fbel, out_f);
+                if (cb >= 0 && ((cb & 63) == 63 || cb == N - 1)) {
+                    const int col = cb - 63 + lane;
+                    if (col >= (cb & ~63)) slot[col] = make_int2(out_h, out_f);
+                }
+            }
+            if ((t & 4095) == 4095) fold(t & ~4095);
+        }
+        fold((T - 1) & ~4095);
+        block_fence();
+        const int smax = uni(wave_max(ls));
+        if (smax > b.s) {
+            const uint64_t m = __ballot(ls == smax);
+            const int wl = __ffsll((unsigned long long)m) - 1;
+            b.s = smax;
+            b.i = __builtin_amdgcn_readlane(li, wl);
+            b.j = __builtin_amdgcn_readlane(lj, wl);
+        }
+        if (REV && b.s >= target) break;
+    }
+    return b;
+}
+
+// ------------------------------------------------------------------ per-item drivers
+__device__ __forceinline__ void write_result(sw_result* out, int pid, int S, int qs, int qe, int rs, int re)
+{
+    sw_result r;
+    if (S > 0) {
+        r.score = S;
+        r.q_start = qs;
+        r.q_end = qe;
+        r.r_start = rs;
+        r.r_end = re;
+    } else {
+        r.score = 0;
+        r.q_start = r.q_end = r.r_start = r.r_end = -1;
+    }
+    out[pid] = r;
+}
+
+template <int R>
+__device__ void do_inter_group(const Args& a, int first, int count, uint8_t* prof, uint32_t* slot)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int pid = -1, m = 0, n = 0;
+    int64_t qoff = 0, roff = 0;
+    if (lane < count) {
+        pid = a.perm[first + lane];
+        if (pid < 0 || pid >= a.n_pairs) pid = -1;
+    }
+    if (pid >= 0) {
+        const int qi = a.pairs[2 * pid], ri = a.pairs[2 * pid + 1];
+        qoff = a.offsets[qi];
+        m = (int)(a.offsets[qi + 1] - qoff);
+        roff = a.offsets[ri];
+        n = (int)(a.offsets[ri + 1] - roff);
+    }
+    const Best f = inter_sweep<R, false>(a, prof, slot, qoff, m, roff, n, 0);
+    const bool has = f.s > 0;
+    const Best r = inter_sweep<R, true>(a, prof, slot, qoff + (has ? f.i : 0), has ? f.i + 1 : 0,
+                                        roff + (has ? f.j : 0), has ? f.j + 1 : 0, f.s);
+    if (pid >= 0) {
+        if (has && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+        write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
+    }
+}
+
+template <int R>
+__device__ void do_wave_pair(const Args& a, int pid, uint8_t* prof, int2* slot)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    pid = uni(pid);
+    if (pid < 0 || pid >= a.n_pairs) {
+        if (lane == 0) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+        return;
+    }
+    const int qi = uni(a.pairs[2 * pid]), ri = uni(a.pairs[2 * pid + 1]);
+    const int64_t qoff = uni64(a.offsets[qi]), roff = uni64(a.offsets[ri]);
+    const int m = uni((int)(a.offsets[qi + 1] - qoff)), n = uni((int)(a.offsets[ri + 1] - roff));
+    const Best f = wave_sweep<R, false>(a, prof, slot, qoff, m, roff, n, 0);
+    Best r{0, -1, -1};
+    if (f.s > 0) r = wave_sweep<R, true>(a, prof, slot, qoff + f.i, f.i + 1, roff + f.j, f.j + 1, f.s);
+    if (lane == 0) {
+        if (f.s > 0 && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+        write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+template <int R>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_persistent(Args a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
+    // the counters come from the scan; clamp them so that a bookkeeping error
+    // can never index past the permutation
+    const int n_wave = min(max(a.counters[kCntWave], 0), (int)a.n_pairs);
+    const int n_inter = min(max(a.counters[kCntInter], 0), (int)a.n_pairs - n_wave);
+    const int n_groups = (n_inter + kWave - 1) / kWave;
+    const int total = n_wave + n_groups;
+    for (;;) {
+        int item = 0;
+        if ((threadIdx.x & (kWave - 1)) == 0) item = atomicAdd(&a.counters[kCntHead], 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= total) break;
+        if (item < n_wave) {
+            do_wave_pair<R>(a, a.perm[item], lds, reinterpret_cast<int2*>(slot));
+        } else {
+            const int g = item - n_wave;
+            do_inter_group<R>(a, n_wave + g * kWave, min(kWave, n_inter - g * kWave), lds, slot);
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_plain_inter(Args a, int first, int count)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
+    first = max(first, 0);
+    count = min(count, (int)a.n_pairs - first);
+    const int groups = (count + kWave - 1) / kWave;
+    for (int g = blockIdx.x; g < groups; g += gridDim.x)
+        do_inter_group<R>(a, first + g * kWave, min(kWave, count - g * kWave), lds, slot);
+}
+
+template <int R>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_plain_wave(Args a, int first, int count)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
+    first = max(first, 0);
+    count = min(count, (int)a.n_pairs - first);
+    for (int p = blockIdx.x; p < count; p += gridDim.x)
+        do_wave_pair<R>(a, a.perm[first + p], lds, reinterpret_cast<int2*>(slot));
+}
+
+// ASCII -> packed.  Thread t writes the 32 residues of high word t: positions
+// [32 t - kGuardRes, 32 t + 32 - kGuardRes).
+__global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, uint32_t* __restrict__ blk,
+                       int64_t n_hib_words, int32_t* err)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_hib_words) return;
+    const int64_t p0 = 32 * t - kGuardRes;
+    uint32_t nib[4] = {0, 0, 0, 0}, hib = 0;
+    bool bad = false;
+    for (int k = 0; k < 32; ++k) {
+        const int64_t p = p0 + k;
+        uint32_t c = kPadCode;
+        if (p >= 0 && p < n) {
+            c = c_tables.ascii[ascii[p]];
+            if (c == 0xFFu) {
+                c = kPadCode;
+                bad = true;
+            }
+        }
+        nib[k >> 3] |= (c & 15u) << (4 * (k & 7));
+        hib |= (c >> 4) << k;
+    }
+    const int64_t blkidx = t >> 3, sub = t & 7;  // 8 high words (256 residues) per block
+    uint32_t* b = blk + blkidx * 40;
+    for (int k = 0; k < 4; ++k) b[4 * sub + k] = nib[k];
+    b[32 + sub] = hib;
+    if (bad) atomicOr((unsigned*)err, (unsigned)kErrCode);
+}
+
+// ------------------------------------------------------------------ work cells
+__device__ __forceinline__ int ceil_log2(int64_t x)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < x) ++b;
+    return b;
+}
+
+// Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
+// (length bucket, 16*log2(m*n)).  Returns -1 for pairs that need no work and
+// -2 for invalid pairs (their result is written here).
+__device__ __forceinline__ int classify(const Args& a, int64_t k)
+{
+    const int64_t qi = a.pairs[2 * k], ri = a.pairs[2 * k + 1];
+    sw_result bad;
+    bad.score = bad.q_start = bad.q_end = bad.r_start = bad.r_end = -1;
+    if (qi < 0 || qi >= a.n_seqs || ri < 0 || ri >= a.n_seqs) {
+        a.out[k] = bad;
+        return -2;
+    }
+    const int64_t q0 = a.offsets[qi], q1 = a.offsets[qi + 1], r0 = a.offsets[ri], r1 = a.offsets[ri + 1];
+    const int64_t nres = a.hdr->n_residues;
+    if (q0 < 0 || r0 < 0 || q1 < q0 || r1 < r0 || q1 > nres || r1 > nres || q1 - q0 > SW_MAX_SEQ_LEN ||
+        r1 - r0 > SW_MAX_SEQ_LEN) {
+        a.out[k] = bad;
+        return -2;
+    }
+    const int64_t m = q1 - q0, n = r1 - r0;
+    if (m == 0 || n == 0) {
+        sw_result z;
+        z.score = 0;
+        z.q_start = z.q_end = z.r_start = z.r_end = -1;
+        a.out[k] = z;
+        return -1;
+    }
+    const int64_t mx = m > n ? m : n;
+    if (mx <= a.inter_max_len) {
+        const int s = (int)((m + a.rows_per_lane - 1) / a.rows_per_lane);
+        const int c = (int)((n + 7) / 8);
+        return (s - 1) * kMaxInterChunks + (c - 1);
+    }
+    const int64_t cost = m * n;
+    const int msb = 63 - __clzll((unsigned long long)cost);
+    const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15) : 0;
+    const int cb = min(kWaveCostBins - 1, 16 * msb + frac);
+    return kInterCells + ceil_log2(mx) * kWaveCostBins + cb;
+}
+
+__global__ void k_zero_cells(Args a)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNumCells; i += gridDim.x * blockDim.x)
+        a.cell_count[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntHead] = 0;
+}
+
+__global__ void k_prepare(Args a)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int cell = classify(a, k);
+        a.pair_cell[k] = cell;
+        if (cell >= 0) atomicAdd(&a.cell_count[cell], 1);
+        else if (cell == -2) atomicOr((unsigned*)a.err, (unsigned)kErrRange);
+    }
+}
+
+// Single block: exclusive scan of the cell counts in rank order; the counts
+// become scatter cursors; counters get the number of long and short pairs.
+__global__ __launch_bounds__(1024) void k_scan(Args a)
+{
+    __shared__ int part[1024];
+    __shared__ int nw[1024];
+    const int t = threadIdx.x;
+    constexpr int per = (kNumCells + 1023) / 1024;
+    const int lo = t * per, hi = min(kNumCells, lo + per);
+    int sum = 0, waves = 0;
+    for (int rk = lo; rk < hi; ++rk) {
+        const int cell = a.rank_cell[rk];
+        const int c = a.cell_count[cell];
+        sum += c;
+        if (cell >= kInterCells) waves += c;
+    }
+    part[t] = sum;
+    nw[t] = waves;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = t >= o ? part[t - o] : 0;
+        const int w = t >= o ? nw[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        nw[t] += w;
+        __syncthreads();
+    }
+    int run = part[t] - sum;  // exclusive prefix
+    for (int rk = lo; rk < hi; ++rk) {
+        const int cell = a.rank_cell[rk];
+        const int c = a.cell_count[cell];
+        a.rank_start[rk] = run;
+        a.cell_count[cell] = run;
+        run += c;
+    }
+    if (t == 1023) {
+        a.rank_start[kNumCells] = part[1023];
+        a.counters[kCntWave] = nw[1023];
+        a.counters[kCntInter] = part[1023] - nw[1023];
+    }
+}
+
+__global__ void k_scatter(Args a)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int cell = a.pair_cell[k];
+        if (cell >= 0) a.perm[atomicAdd(&a.cell_count[cell], 1)] = (int32_t)k;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * R; }
+
+int64_t slot_words(int R, int inter_max_len)
+{
+    (void)R;
+    const int64_t inter = (int64_t)((inter_max_len + 7) / 8) * kWave * 8;
+    const int64_t wave = (int64_t)(SW_MAX_SEQ_LEN + 1) * 2;
+    return inter > wave ? inter : wave;
+}
+
+__global__ void k_pack_header(PackedHeader* h, int64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        h->magic = kPackMagic;
+        h->version = 1;
+        h->n_residues = n;
+        h->n_blocks = (kGuardRes + n + kTailRes + 255) / 256 + 1;
+        h->total_bytes = kHeaderBytes + h->n_blocks * 160;
+    }
+}
+
+hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err, hipStream_t stream)
+{
+    PackedHeader* h = reinterpret_cast<PackedHeader*>(packed);
+    uint32_t* blk = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(packed) + kHeaderBytes);
+    const int64_t n_hib_words = packed_blocks(n) * 8;
+    const int threads = 256;
+    const int64_t blocks = (n_hib_words + threads - 1) / threads;
+    hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(64), 0, stream, h, n);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(threads), 0, stream, (const uint8_t*)ascii, n, blk,
+                       n_hib_words, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const Args& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_cells, dim3(64), dim3(256), 0, stream, a);
+    const int64_t blocks = std::min<int64_t>((a.n_pairs + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, a);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_persistent_r(const Args& a, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_persistent<R>, dim3(grid), dim3(kWave), lds_bytes(R), stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream)
+{
+    switch (a.rows_per_lane) {
+    case 16: return launch_persistent_r<16>(a, grid, stream);
+    case 32: return launch_persistent_r<32>(a, grid, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int R>
+static hipError_t launch_plain_r(const Args& a, bool wave, int first, int count, int grid, hipStream_t stream)
+{
+    if (wave)
+        hipLaunchKernelGGL(k_plain_wave<R>, dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
+    else
+        hipLaunchKernelGGL(k_plain_inter<R>, dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const Args& a, bool wave, int first, int count, int grid, hipStream_t stream)
+{
+    switch (a.rows_per_lane) {
+    case 16: return launch_plain_r<16>(a, wave, first, count, grid, stream);
+    case 32: return launch_plain_r<32>(a, wave, first, count, grid, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t set_kernel_attributes()
+{
+    hipError_t e = hipSuccess;
+    const int bytes32 = (int)lds_bytes(32);
+    e = hipFuncSetAttribute((const void*)k_persistent<32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_plain_inter<32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_plain_wave<32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
+    return e;
+}
+
+}  // namespace swk

@@ -1,0 +1,95 @@
+// Internal declarations shared by the device code (sw_device.hip) and the
+// host layer (sw_api.cpp).  Not part of the public interface.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/sw.h"
+
+namespace swk {
+
+// ---------------------------------------------------------------- packed format
+// A packed buffer is a 256-byte header followed by 160-byte blocks.  Block b
+// holds residue positions [256 b - kGuardRes, 256 (b+1) - kGuardRes):
+//   words 0..31: nibble plane, residue at block offset o -> bits 4*(o&7).. of word o>>3
+//   words 32..39: high plane,  residue at block offset o -> bit o&31 of word 32 + (o>>5)
+// code = nibble | high << 4, in the library's own symbol order.  The guard of
+// kGuardRes residues before position 0 and the slack after the last residue
+// keep every 8-, 16- and 32-residue window that overlaps a sequence inside
+// the buffer.  Nothing in the layout depends on the number of residues, so
+// the aligner needs only the buffer pointer.
+constexpr uint32_t kPackMagic = 0x35575350u;  // "PSW5"
+constexpr int kGuardRes = 64;
+constexpr int kTailRes = 192;
+constexpr int kHeaderBytes = 256;
+constexpr int kNumSym = 24;
+constexpr int kPadCode = 24;  // beyond a sequence end; scores -128 against everything
+constexpr int kNumCodes = 25;
+
+struct PackedHeader {
+    uint32_t magic;
+    uint32_t version;
+    int64_t n_residues;
+    int64_t n_blocks;
+    int64_t total_bytes;
+};
+
+inline int64_t packed_blocks(int64_t n) { return (kGuardRes + n + kTailRes + 255) / 256 + 1; }
+inline size_t packed_bytes(int64_t n) { return (size_t)kHeaderBytes + (size_t)packed_blocks(n) * 160; }
+
+// ---------------------------------------------------------------- work layout
+constexpr int kWave = 64;
+constexpr int kMaxInterStrips = 64;    // ceil(inter_max_len / rows_per_lane) <= this
+constexpr int kMaxInterChunks = 128;   // ceil(inter_max_len / 8) <= this
+constexpr int kMaxInterLen = 1024;
+constexpr int kWaveCostBins = 512;     // floor(16 * log2(m*n)) for long pairs
+constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
+constexpr int kInterCells = kMaxInterStrips * kMaxInterChunks;
+constexpr int kWaveCells = kNumLenBuckets * kWaveCostBins;
+constexpr int kNumCells = kInterCells + kWaveCells;
+
+// counters[] slots in the workspace
+enum {
+    kCntHead = 0,   // persistent work-queue head
+    kCntWave = 1,   // number of long pairs (one wave each)
+    kCntInter = 2,  // number of lane-per-pair pairs
+    kNumCounters = 16
+};
+enum { kErrRange = 1, kErrCode = 2, kErrInternal = 4 };
+
+struct Args {
+    const uint32_t* blk;       // first block of the packed buffer
+    const PackedHeader* hdr;   // its header
+    const int64_t* offsets;
+    int64_t n_seqs;
+    const int32_t* pairs;
+    int64_t n_pairs;
+    sw_result* out;
+    int32_t* pair_cell;        // [n_pairs] work cell of each pair (-1 none, -2 invalid)
+    int32_t* perm;             // [n_pairs] pair indices sorted by rank of their cell
+    int32_t* cell_count;       // [kNumCells] histogram, then scatter cursors
+    const int32_t* rank_cell;  // [kNumCells] cell at each rank
+    int32_t* rank_start;       // [kNumCells + 1] first perm position of each rank
+    int32_t* counters;         // [kNumCounters]
+    int32_t* err;              // device error bits of this device (kErr*)
+    uint32_t* scratch;         // boundary rows, one slot per resident block
+    int64_t slot_words;        // 32-bit words per slot
+    int32_t go, ge;
+    int32_t rows_per_lane;
+    int32_t inter_max_len;
+};
+
+// launchers (sw_device.hip); all asynchronous on `stream`
+hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err, hipStream_t stream);
+hipError_t launch_prepare(const Args& a, hipStream_t stream);  // zero, classify, scan, scatter
+hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream);
+hipError_t launch_plain(const Args& a, bool wave, int first, int count, int grid, hipStream_t stream);
+hipError_t set_kernel_attributes();
+size_t lds_bytes(int rows_per_lane);
+int64_t slot_words(int rows_per_lane, int inter_max_len);
+void matrix_ncbi(int8_t out[kNumSym * kNumSym], char letters[kNumSym + 1]);
+const char* code_order();
+
+}  // namespace swk

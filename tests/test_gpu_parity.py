@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for
+bit on all five int32 outputs, on seeded synthetic inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import proteins as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sw():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    import paper_2303_01845_amd as lib
+    lib.lib()
+    lib.set_tuning(16, 1024, 0)
+    return lib
+
+
+def gpu_align(sw, ps, go=11, ge=1, flags=0):
+    import torch
+    b = sw.Batch(ps.ascii, ps.offsets)
+    out = b.align(ps.pairs, go, ge, flags)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def expect(ps, go=11, ge=1):
+    return oracle.batch_ascii(ps.ascii, ps.offsets, ps.pairs, go, ge)
+
+
+def assert_same(got, exp, ps, label):
+    bad = np.flatnonzero((got != exp).any(axis=1))
+    if len(bad):
+        k = int(bad[0])
+        q, r = ps.pairs[k]
+        L = ps.lengths()
+        raise AssertionError("%s: %d of %d pairs differ; first pair %d (m=%d n=%d): gpu %s oracle %s"
+                             % (label, len(bad), len(got), k, L[q], L[r], got[k].tolist(),
+                                exp[k].tolist()))
+
+
+def pairset_from_strings(pairs_str):
+    seqs = []
+    for q, r in pairs_str:
+        seqs += [q, r]
+    L = np.array([len(s) for s in seqs], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(L)])
+    asc = np.frombuffer(("".join(seqs)).encode(), dtype=np.uint8).copy()
+    prs = np.arange(2 * len(pairs_str), dtype=np.int32).reshape(-1, 2)
+    return P.PairSet(asc, offs, prs, "strings")
+
+
+def test_small_config_all_forms(sw):
+    ps = P.config_small()
+    exp = expect(ps)
+    for flags, label in [(0, "persistent+graph"), (sw.NO_GRAPH, "persistent"), (sw.PLAIN, "plain")]:
+        say("small config, %s" % label)
+        assert_same(gpu_align(sw, ps, flags=flags), exp, ps, label)
+
+
+def test_golden_fixture_cases(sw):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_cases.tsv")
+    rows = [l.rstrip("\n").split("\t") for l in open(path) if l.strip() and not l.startswith("#")]
+    by_gap = {}
+    for q, r, go, ge, *e in rows:
+        by_gap.setdefault((int(go), int(ge)), []).append((q, r, [int(x) for x in e]))
+    for (go, ge), cases in by_gap.items():
+        say("golden cases gap %d/%d" % (go, ge))
+        ps = pairset_from_strings([(q, r) for q, r, _ in cases])
+        got = gpu_align(sw, ps, go, ge)
+        assert_same(got, np.array([e for _, _, e in cases], dtype=np.int32), ps, "golden")
+
+
+def adversarial_set(seed, n, max_len):
+    rng = np.random.default_rng(seed)
+    letters = np.frombuffer(b"ARNDCQEGHILKMFPSTWYVBZX*", dtype=np.uint8)
+    out = []
+    for t in range(n):
+        kind = t % 6
+        m, nn = (int(x) for x in rng.integers(1, max_len + 1, 2))
+        if kind == 0:
+            a = letters[rng.integers(0, 24)]
+            q, r = bytes([a]) * m, bytes([a]) * nn
+        elif kind == 1:
+            ab = rng.choice(letters[:20], 2, replace=False)
+            q, r = rng.choice(ab, m).tobytes(), rng.choice(ab, nn).tobytes()
+        elif kind == 2:
+            u = rng.choice(letters[:20], int(rng.integers(1, 6))).tobytes()
+            q, r = (u * (max_len // len(u) + 2))[:m], (u * (max_len // len(u) + 2))[1:nn + 1]
+        elif kind == 3:
+            q = rng.choice(letters, int(rng.integers(1, 4))).tobytes()
+            r = rng.choice(letters, int(rng.integers(1, 4))).tobytes()
+        elif kind == 4:
+            q = rng.choice(letters[:20], m).tobytes()
+            r = q[: nn // 2] + rng.choice(letters[:20], int(rng.integers(1, 9))).tobytes() + q[nn // 2:]
+        else:
+            q, r = rng.choice(letters, m).tobytes(), rng.choice(letters, nn).tobytes()
+        out.append((q.decode(), r.decode()))
+    return pairset_from_strings(out)
+
+
+@pytest.mark.parametrize("gaps", [(11, 1), (2, 1), (1, 0), (3, 3), (11, 2), (10 ** 6, 10 ** 6)])
+def test_adversarial_short(sw, gaps):
+    ps = adversarial_set(100 + gaps[0], 700, 300)
+    say("adversarial short gap %s" % (gaps,))
+    assert_same(gpu_align(sw, ps, *gaps), expect(ps, *gaps), ps, "adversarial %s" % (gaps,))
+
+
+def test_adversarial_long_wavefront(sw):
+    # every pair longer than the lane-per-pair limit: one wave per pair
+    ps = adversarial_set(7, 36, 3000)
+    keep = [k for k in range(ps.n_pairs) if max(ps.lengths()[ps.pairs[k]]) > 1024]
+    ps = ps.subset(keep)
+    say("adversarial long: %d pairs" % ps.n_pairs)
+    for gaps in [(11, 1), (2, 1)]:
+        assert_same(gpu_align(sw, ps, *gaps), expect(ps, *gaps), ps, "long %s" % (gaps,))
+
+
+def test_lognormal_prefix_full_parity(sw):
+    ps = P.config_1m(65536)
+    say("lognormal prefix: %d pairs %.2f Gcells" % (ps.n_pairs, ps.cells() / 1e9))
+    exp = expect(ps)
+    assert_same(gpu_align(sw, ps), exp, ps, "lognormal persistent")
+    assert_same(gpu_align(sw, ps, flags=sw.PLAIN), exp, ps, "lognormal plain")
+
+
+def test_heavy_tail_mix(sw):
+    ps = P.config_batching(1500)
+    say("heavy tail: %d pairs %.2f Gcells, longest %d" % (ps.n_pairs, ps.cells() / 1e9,
+                                                          ps.lengths().max()))
+    assert_same(gpu_align(sw, ps), expect(ps), ps, "heavy tail")
+
+
+def test_tuning_does_not_change_results(sw):
+    ps = P.concat([P.config_small(), adversarial_set(3, 300, 1500)])
+    ref = None
+    try:
+        for R, im, bpc in [(16, 1024, 0), (32, 1024, 0), (16, 64, 0), (32, 256, 2), (16, 512, 1)]:
+            sw.set_tuning(R, im, bpc)
+            say("tuning R=%d inter_max=%d bpc=%d" % (R, im, bpc))
+            got = gpu_align(sw, ps)
+            if ref is None:
+                ref = got
+                assert_same(got, expect(ps), ps, "tuning reference")
+            assert (got == ref).all(), (R, im, bpc)
+    finally:
+        sw.set_tuning(16, 1024, 0)
+
+
+def test_permuted_pairs(sw):
+    ps = P.config_small()
+    rng = np.random.default_rng(9)
+    perm = rng.permutation(ps.n_pairs)
+    ps2 = P.PairSet(ps.ascii, ps.offsets, ps.pairs[perm].copy(), "perm")
+    a = gpu_align(sw, ps)
+    b = gpu_align(sw, ps2)
+    assert (a[perm] == b).all()
+
+
+def test_empty_invalid_and_bad_residues(sw):
+    import torch
+    seqs = ["", "ACDEFGHIK", "WWWW", "MKV"]
+    L = np.array([len(s) for s in seqs], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(L)])
+    asc = np.frombuffer("".join(seqs).encode(), dtype=np.uint8).copy()
+    pairs = np.array([[0, 1], [1, 0], [2, 2], [1, 4], [-1, 2], [3, 1]], dtype=np.int32)
+    b = sw.Batch(asc, offs)
+    with pytest.raises(sw.SwError) as e:
+        b.align(pairs, flags=sw.VALIDATE)
+    assert e.value.status == sw.SW_ERANGE
+    out = b.align(pairs).cpu().numpy()
+    with pytest.raises(sw.SwError) as e:      # raised again by the non-validating call
+        sw.check()
+    assert e.value.status == sw.SW_ERANGE
+    sw.check()                                 # and cleared by the check
+    assert out[0].tolist() == [0, -1, -1, -1, -1]
+    assert out[1].tolist() == [0, -1, -1, -1, -1]
+    assert out[2].tolist() == [44, 0, 3, 0, 3]
+    assert out[3].tolist() == [-1] * 5 and out[4].tolist() == [-1] * 5
+    assert tuple(out[5]) == oracle.align(b"MKV", b"ACDEFGHIK")
+
+
+def test_invalid_residue_reported(sw):
+    with pytest.raises(sw.SwError) as e:
+        sw.Batch(np.frombuffer(b"ACDJKL", dtype=np.uint8), np.array([0, 3, 6])).align(
+            np.array([[0, 1]], dtype=np.int32), flags=sw.VALIDATE)
+    assert e.value.status == sw.SW_ECODE
+
+
+def test_maximum_length_pairs(sw):
+    rng = np.random.default_rng(11)
+    a = P.background(rng, 65535)
+    b = np.concatenate([a[30000:30400], P.background(rng, 100)])
+    c = P.background(rng, 20)
+    seqs = [a, b, c]
+    L = np.array([len(s) for s in seqs], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(L)])
+    ps = P.PairSet(np.concatenate(seqs), offs, np.array([[0, 1], [1, 0], [0, 2], [2, 0]], np.int32), "max")
+    say("maximum length pairs")
+    assert_same(gpu_align(sw, ps), expect(ps), ps, "max length")
