@@ -120,6 +120,19 @@ SW_API int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, in
                    sw_result* out_dev, void* stream, uint32_t flags);
 
 /*
+ * Align pairs drawn from two sequence sets, each packed by sw_pack into its
+ * own buffer (for instance a query batch against a reference set that stays
+ * resident in HBM).  pairs_dev[2k] indexes the query set (n_q sequences,
+ * q_offsets_dev int64[n_q + 1]) and pairs_dev[2k+1] the reference set.
+ * Results, flags and errors as for sw_batch_align, which is this call with
+ * both sets equal.
+ */
+SW_API int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                         const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
+                         const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring,
+                         sw_result* out_dev, void* stream, uint32_t flags);
+
+/*
  * Synchronise `stream`, then return and clear the device-detected errors
  * (SW_ERANGE, SW_ECODE) raised by earlier calls on the current device.
  */
@@ -142,11 +155,75 @@ SW_API int sw_set_tuning(const sw_tuning* t);
 SW_API int sw_get_tuning(sw_tuning* t);
 
 /*
+ * Autotuner: time sw_batch_align (persistent form) on this workload for every
+ * candidate kernel shape (rows_per_lane 16/32, inter_max_len 256/512/1024 --
+ * the length above which a pair gets a whole wave instead of one lane --
+ * and blocks_per_cu occupancy-derived or 2), `reps` timed runs each, require
+ * every shape to give byte-identical results, keep the fastest as the current
+ * tuning and report it in *chosen (and its time per call in *best_ms, may be
+ * NULL).  Synchronises `stream`; out_dev receives the results.  On error the
+ * previous tuning is restored; results that differ between shapes return
+ * SW_EDEVICE.
+ */
+SW_API int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs,
+                       const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring,
+                       sw_result* out_dev, void* stream, int32_t reps, sw_tuning* chosen, float* best_ms);
+
+/*
  * The library's substitution matrix in the alphabet order above
  * (scores[24*q + r], query symbol q, reference symbol r) and the alphabet
  * itself (25 bytes including the terminating zero).  Host memory.
  */
 SW_API int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching against a reference set resident in HBM.  The server
+ * keeps `max_slots` HIP streams, each with its own alignment workspace, and an
+ * arena of hbm_budget_bytes for the device state of requests in flight
+ * (query ASCII, packed queries, offsets, candidate pairs, results; see
+ * sw_server_request_bytes).  A request is admitted when a slot is free and
+ * its state fits in the part of the arena not in use; admitted requests run
+ * concurrently, so work from a request that arrives while others are on the
+ * GPU overlaps with theirs.  Results of a request do not depend on what else
+ * is in flight.  The reference buffers (from sw_pack) stay owned by the
+ * caller and must outlive the server.  Servers are not shareable between
+ * devices; calls on one server are serialised by the server.
+ */
+typedef struct sw_server sw_server;
+
+/* Errors: SW_EINVAL (bad argument or scoring), SW_ENOMEM (arena allocation),
+ * SW_EDEVICE. */
+SW_API int sw_server_create(const void* refs_packed_dev, const int64_t* ref_offsets_dev, int64_t n_refs,
+                            const sw_scoring* scoring, size_t hbm_budget_bytes, int max_slots,
+                            sw_server** server);
+
+/* Submit n_q query sequences (host ASCII, host int64 offsets[n_q + 1]) with
+ * n_cand candidate pairs (host int32 [query index within the request,
+ * reference index]).  On SW_OK *ticket identifies the request and out_host
+ * (host, n_cand results) is written when the request completes (poll/wait);
+ * the library copies the inputs before returning.  SW_EAGAIN: no free slot
+ * or not enough free budget now, retry after a completion.  SW_ENOMEM: the
+ * request can never fit the budget.  SW_ECANCELED after destroy began. */
+SW_API int sw_server_submit(sw_server* server, const char* q_ascii, const int64_t* q_offsets, int64_t n_q,
+                            const int32_t* cand, int64_t n_cand, sw_result* out_host, uint64_t* ticket);
+
+/* SW_OK once the request is complete (results copied, resources freed; the
+ * ticket is then retired), SW_EAGAIN while it runs, SW_EINVAL for an unknown
+ * ticket. */
+SW_API int sw_server_poll(sw_server* server, uint64_t ticket);
+
+/* Poll until complete or until timeout_us elapses (SW_ETIMEOUT); a negative
+ * timeout waits without limit. */
+SW_API int sw_server_wait(sw_server* server, uint64_t ticket, int64_t timeout_us);
+
+/* Requests in flight, arena bytes in use and the budget (any pointer may be NULL). */
+SW_API int sw_server_stats(sw_server* server, int64_t* inflight, int64_t* bytes_in_use, int64_t* budget);
+
+/* Arena bytes a request of this size needs (0 for negative arguments). */
+SW_API size_t sw_server_request_bytes(int64_t n_residues, int64_t n_q, int64_t n_cand);
+
+/* Wait for every request in flight, then free the server. */
+SW_API int sw_server_destroy(sw_server* server);
 
 /* Text of a status code; never NULL. */
 SW_API const char* sw_strerror(int status);

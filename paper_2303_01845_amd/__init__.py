@@ -31,8 +31,10 @@ VALIDATE = 2
 NO_GRAPH = 4
 
 # every function the C header declares
-EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_check", "sw_set_tuning",
-           "sw_get_tuning", "sw_matrix", "sw_strerror", "sw_last_device_error")
+EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_check", "sw_set_tuning",
+           "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
+           "sw_server_submit", "sw_server_poll", "sw_server_wait", "sw_server_stats",
+           "sw_server_request_bytes", "sw_server_destroy")
 
 
 class SwError(RuntimeError):
@@ -73,9 +75,29 @@ def lib():
         L.sw_batch_align.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+        L.sw_align_sets.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
         L.sw_check.argtypes = [ctypes.c_void_p]
+        L.sw_server_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.POINTER(Scoring), ctypes.c_size_t, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.sw_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.sw_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        L.sw_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64]
+        L.sw_server_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.sw_server_request_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        L.sw_server_request_bytes.restype = ctypes.c_size_t
+        L.sw_server_destroy.argtypes = [ctypes.c_void_p]
         L.sw_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.sw_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.sw_autotune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                  ctypes.c_int64, ctypes.POINTER(Scoring), ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float)]
         L.sw_matrix.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_char_p]
         L.sw_strerror.argtypes = [ctypes.c_int]
         L.sw_strerror.restype = ctypes.c_char_p
@@ -137,6 +159,25 @@ def align(packed, offsets, pairs, gap_open: int = 11, gap_extend: int = 1, flags
     return out
 
 
+def align_sets(q_packed, q_offsets, r_packed, r_offsets, pairs, gap_open: int = 11,
+               gap_extend: int = 1, flags: int = PERSISTENT, out=None, stream=None):
+    """Like align with queries and references in two packed buffers."""
+    import torch
+    n_pairs = int(pairs.shape[0]) if pairs.dim() == 2 else int(pairs.numel() // 2)
+    if out is None:
+        out = torch.empty((n_pairs, 5), dtype=torch.int32, device=pairs.device)
+    assert q_offsets.dtype == torch.int64 and r_offsets.dtype == torch.int64
+    assert pairs.dtype == torch.int32 and out.dtype == torch.int32 and pairs.is_contiguous()
+    sc = Scoring(0, int(gap_open), int(gap_extend))
+    _check(lib().sw_align_sets(ctypes.c_void_p(q_packed.data_ptr()), ctypes.c_void_p(q_offsets.data_ptr()),
+                               int(q_offsets.numel()) - 1, ctypes.c_void_p(r_packed.data_ptr()),
+                               ctypes.c_void_p(r_offsets.data_ptr()), int(r_offsets.numel()) - 1,
+                               ctypes.c_void_p(pairs.data_ptr()), n_pairs, ctypes.byref(sc),
+                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), int(flags)),
+           "sw_align_sets")
+    return out
+
+
 def check(stream=None):
     """Synchronise and raise for device-detected errors (SW_ERANGE / SW_ECODE)."""
     _check(lib().sw_check(_stream_ptr(stream)), "sw_check")
@@ -152,6 +193,25 @@ def get_tuning() -> dict:
     _check(lib().sw_get_tuning(ctypes.byref(t)), "sw_get_tuning")
     return {"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
             "blocks_per_cu": t.blocks_per_cu}
+
+
+def autotune(packed, offsets, pairs, gap_open: int = 11, gap_extend: int = 1, reps: int = 3,
+             out=None, stream=None):
+    """Pick and keep the fastest kernel shape for this workload (results must
+    be identical across shapes).  Returns (tuning dict, ms per call)."""
+    import torch
+    n_pairs = int(pairs.shape[0])
+    if out is None:
+        out = torch.empty((n_pairs, 5), dtype=torch.int32, device=pairs.device)
+    t = Tuning()
+    ms = ctypes.c_float()
+    sc = Scoring(0, int(gap_open), int(gap_extend))
+    _check(lib().sw_autotune(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                             int(offsets.numel()) - 1, ctypes.c_void_p(pairs.data_ptr()), n_pairs,
+                             ctypes.byref(sc), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), int(reps),
+                             ctypes.byref(t), ctypes.byref(ms)), "sw_autotune")
+    return ({"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
+             "blocks_per_cu": t.blocks_per_cu}, float(ms.value))
 
 
 def matrix():

@@ -114,9 +114,12 @@ Ordering make_ordering(int R, int inter_max)
 }
 
 struct GraphKey {
-    const void* packed;
-    const void* offsets;
-    int64_t n_seqs;
+    const void* q_packed;
+    const void* q_offsets;
+    int64_t n_q;
+    const void* r_packed;
+    const void* r_offsets;
+    int64_t n_r;
     const void* pairs;
     int64_t n_pairs;
     int32_t go, ge;
@@ -124,9 +127,10 @@ struct GraphKey {
     int R, inter_max, grid;
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(packed, offsets, n_seqs, pairs, n_pairs, go, ge, out, R, inter_max, grid) <
-               std::tie(o.packed, o.offsets, o.n_seqs, o.pairs, o.n_pairs, o.go, o.ge, o.out, o.R, o.inter_max,
-                        o.grid);
+        return std::tie(q_packed, q_offsets, n_q, r_packed, r_offsets, n_r, pairs, n_pairs, go, ge, out, R,
+                        inter_max, grid) < std::tie(o.q_packed, o.q_offsets, o.n_q, o.r_packed, o.r_offsets,
+                                                    o.n_r, o.pairs, o.n_pairs, o.go, o.ge, o.out, o.R,
+                                                    o.inter_max, o.grid);
     }
 };
 
@@ -309,17 +313,20 @@ int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, size_t 
     return SW_OK;
 }
 
-int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs, const int32_t* pairs_dev,
-                   int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream_, uint32_t flags)
+int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                  const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+                  const sw_scoring* scoring, sw_result* out_dev, void* stream_, uint32_t flags)
 {
-    if (!scoring || n_pairs < 0 || n_seqs < 0) return SW_EINVAL;
+    if (!scoring || n_pairs < 0 || n_q < 0 || n_r < 0) return SW_EINVAL;
     if (flags & ~(SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH)) return SW_EINVAL;
     if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
         scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
         return SW_EINVAL;
     if (n_pairs == 0) return SW_OK;
-    if (!packed_dev || !offsets_dev || !pairs_dev || !out_dev) return SW_EINVAL;
-    if (n_pairs > (int64_t)0x7FFFFFFF - 64 || n_seqs > (int64_t)0x7FFFFFFF) return SW_ERANGE;
+    if (!q_packed_dev || !q_offsets_dev || !r_packed_dev || !r_offsets_dev || !pairs_dev || !out_dev)
+        return SW_EINVAL;
+    if (n_pairs > (int64_t)0x7FFFFFFF - 64 || n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF)
+        return SW_ERANGE;
     hipStream_t stream = (hipStream_t)stream_;
 
     std::lock_guard<std::mutex> lock(g_mutex);
@@ -334,10 +341,14 @@ int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n
 
     Args a;
     std::memset(&a, 0, sizeof(a));
-    a.blk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(packed_dev) + kHeaderBytes);
-    a.hdr = reinterpret_cast<const PackedHeader*>(packed_dev);
-    a.offsets = offsets_dev;
-    a.n_seqs = n_seqs;
+    a.qblk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(q_packed_dev) + kHeaderBytes);
+    a.qhdr = reinterpret_cast<const PackedHeader*>(q_packed_dev);
+    a.q_offsets = q_offsets_dev;
+    a.n_q = n_q;
+    a.rblk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(r_packed_dev) + kHeaderBytes);
+    a.rhdr = reinterpret_cast<const PackedHeader*>(r_packed_dev);
+    a.r_offsets = r_offsets_dev;
+    a.n_r = n_r;
     a.pairs = pairs_dev;
     a.n_pairs = n_pairs;
     a.out = out_dev;
@@ -374,8 +385,8 @@ int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n
             HIP_TRY(launch_prepare(a, stream), "prepare launch");
             HIP_TRY(launch_persistent(a, grid, stream), "persistent launch");
         } else {
-            GraphKey key{packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, a.go, a.ge, out_dev,
-                         d.R, d.inter_max, grid};
+            GraphKey key{q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev,
+                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, grid};
             auto it = w.graphs.find(key);
             if (it == w.graphs.end()) {
                 if (w.graphs.size() >= 16) {
@@ -403,6 +414,13 @@ int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n
     }
     if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
     return SW_OK;
+}
+
+int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs, const int32_t* pairs_dev,
+                   int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
+{
+    return sw_align_sets(packed_dev, offsets_dev, n_seqs, packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs,
+                         scoring, out_dev, stream, flags);
 }
 
 int sw_check(void* stream)
@@ -460,6 +478,93 @@ int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters)
 {
     if (matrix_id != 0 || !scores || !letters) return SW_EINVAL;
     matrix_ncbi(scores, letters);
+    return SW_OK;
+}
+
+int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs, const int32_t* pairs_dev,
+                int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream_, int32_t reps,
+                sw_tuning* chosen, float* best_ms)
+{
+    if (!chosen || n_pairs <= 0) return SW_EINVAL;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (reps < 1) reps = 1;
+    sw_tuning orig{};
+    int rc = sw_get_tuning(&orig);
+    if (rc) return rc;
+    struct Cand {
+        int R, im, bpc;
+    };
+    std::vector<Cand> cands;
+    for (int R : {16, 32})
+        for (int im : {256, 512, 1024})
+            for (int bpc : {0, 2})
+                if ((im + R - 1) / R <= kMaxInterStrips) cands.push_back({R, im, bpc});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    std::vector<sw_result> ref((size_t)n_pairs), cur((size_t)n_pairs);
+    float best = 1e30f;
+    sw_tuning best_t = orig;
+    bool have_ref = false;
+    for (const Cand& c : cands) {
+        sw_tuning t{c.R, c.im, c.bpc};
+        if (c.bpc == 0) {  // back to the occupancy-derived grid
+            std::lock_guard<std::mutex> lock(g_mutex);
+            Device* d = nullptr;
+            if ((rc = get_device(&d))) break;
+            d->bpc_user = 0;
+        }
+        if ((rc = sw_set_tuning(&t))) break;
+        // warm-up run, also the tile-independence check
+        if ((rc = sw_batch_align(packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, scoring, out_dev, stream, 0)))
+            break;
+        if (hipMemcpyAsync(cur.data(), out_dev, sizeof(sw_result) * (size_t)n_pairs, hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            rc = dev_error(hipGetLastError(), "autotune readback");
+            break;
+        }
+        if (!have_ref) {
+            ref = cur;
+            have_ref = true;
+        } else if (std::memcmp(ref.data(), cur.data(), sizeof(sw_result) * (size_t)n_pairs) != 0) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "autotune: results differ between kernel shapes (R=%d inter_max=%d)", c.R, c.im);
+            rc = SW_EDEVICE;
+            break;
+        }
+        (void)hipEventRecord(e0, stream);
+        for (int k = 0; k < reps && rc == SW_OK; ++k)
+            rc = sw_batch_align(packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, scoring, out_dev, stream, 0);
+        (void)hipEventRecord(e1, stream);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = dev_error(hipGetLastError(), "autotune timing");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        (void)sw_set_tuning(&orig);
+        return rc;
+    }
+    if (best_t.blocks_per_cu == 0) {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        Device* d = nullptr;
+        if (get_device(&d) == SW_OK) d->bpc_user = 0;
+    }
+    rc = sw_set_tuning(&best_t);
+    if (rc) return rc;
+    *chosen = best_t;
+    if (best_ms) *best_ms = best;
     return SW_OK;
 }
 

@@ -345,8 +345,8 @@ __device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__
     const int ws = uni(wave_max(my_strips));
     const int wc = uni(wave_max(my_strips > 0 ? my_chunks : 0));
     bool done = my_strips == 0 || (REV && target <= 0);
-    const SeqView qv = seq_view(a.blk, Q0);
-    const SeqView rv = seq_view(a.blk, R0);
+    const SeqView qv = seq_view(a.qblk, Q0);
+    const SeqView rv = seq_view(a.rblk, R0);
     uint4* slot4 = reinterpret_cast<uint4*>(slot) + 2 * lane;
 
     for (int s = 0; s < ws; ++s) {
@@ -459,8 +459,8 @@ __device__ Best wave_sweep(const Args& a, uint8_t* prof, int2* __restrict__ slot
     if (M <= 0 || N <= 0 || (REV && target <= 0)) return b;
     constexpr int kRowsPerStrip = kWave * R;
     const int nstrips = (M + kRowsPerStrip - 1) / kRowsPerStrip;
-    const SeqView qv = seq_view(a.blk, Q0);
-    const SeqView rv = seq_view(a.blk, R0);
+    const SeqView qv = seq_view(a.qblk, Q0);
+    const SeqView rv = seq_view(a.rblk, R0);
 
     for (int s = 0; s < nstrips; ++s) {
         const int rows_left = M - s * kRowsPerStrip;
@@ -587,10 +587,10 @@ __device__ void do_inter_group(const Args& a, int first, int count, uint8_t* pro
     }
     if (pid >= 0) {
         const int qi = a.pairs[2 * pid], ri = a.pairs[2 * pid + 1];
-        qoff = a.offsets[qi];
-        m = (int)(a.offsets[qi + 1] - qoff);
-        roff = a.offsets[ri];
-        n = (int)(a.offsets[ri + 1] - roff);
+        qoff = a.q_offsets[qi];
+        m = (int)(a.q_offsets[qi + 1] - qoff);
+        roff = a.r_offsets[ri];
+        n = (int)(a.r_offsets[ri + 1] - roff);
     }
     const Best f = inter_sweep<R, false>(a, prof, slot, qoff, m, roff, n, 0);
     const bool has = f.s > 0;
@@ -612,8 +612,8 @@ __device__ void do_wave_pair(const Args& a, int pid, uint8_t* prof, int2* slot)
         return;
     }
     const int qi = uni(a.pairs[2 * pid]), ri = uni(a.pairs[2 * pid + 1]);
-    const int64_t qoff = uni64(a.offsets[qi]), roff = uni64(a.offsets[ri]);
-    const int m = uni((int)(a.offsets[qi + 1] - qoff)), n = uni((int)(a.offsets[ri + 1] - roff));
+    const int64_t qoff = uni64(a.q_offsets[qi]), roff = uni64(a.r_offsets[ri]);
+    const int m = uni((int)(a.q_offsets[qi + 1] - qoff)), n = uni((int)(a.r_offsets[ri + 1] - roff));
     const Best f = wave_sweep<R, false>(a, prof, slot, qoff, m, roff, n, 0);
     Best r{0, -1, -1};
     if (f.s > 0) r = wave_sweep<R, true>(a, prof, slot, qoff + f.i, f.i + 1, roff + f.j, f.j + 1, f.s);
@@ -718,14 +718,13 @@ __device__ __forceinline__ int classify(const Args& a, int64_t k)
     const int64_t qi = a.pairs[2 * k], ri = a.pairs[2 * k + 1];
     sw_result bad;
     bad.score = bad.q_start = bad.q_end = bad.r_start = bad.r_end = -1;
-    if (qi < 0 || qi >= a.n_seqs || ri < 0 || ri >= a.n_seqs) {
+    if (qi < 0 || qi >= a.n_q || ri < 0 || ri >= a.n_r) {
         a.out[k] = bad;
         return -2;
     }
-    const int64_t q0 = a.offsets[qi], q1 = a.offsets[qi + 1], r0 = a.offsets[ri], r1 = a.offsets[ri + 1];
-    const int64_t nres = a.hdr->n_residues;
-    if (q0 < 0 || r0 < 0 || q1 < q0 || r1 < r0 || q1 > nres || r1 > nres || q1 - q0 > SW_MAX_SEQ_LEN ||
-        r1 - r0 > SW_MAX_SEQ_LEN) {
+    const int64_t q0 = a.q_offsets[qi], q1 = a.q_offsets[qi + 1], r0 = a.r_offsets[ri], r1 = a.r_offsets[ri + 1];
+    if (q0 < 0 || r0 < 0 || q1 < q0 || r1 < r0 || q1 > a.qhdr->n_residues || r1 > a.rhdr->n_residues ||
+        q1 - q0 > SW_MAX_SEQ_LEN || r1 - r0 > SW_MAX_SEQ_LEN) {
         a.out[k] = bad;
         return -2;
     }

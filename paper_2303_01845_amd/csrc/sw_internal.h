@@ -60,10 +60,14 @@ enum {
 enum { kErrRange = 1, kErrCode = 2, kErrInternal = 4 };
 
 struct Args {
-    const uint32_t* blk;       // first block of the packed buffer
-    const PackedHeader* hdr;   // its header
-    const int64_t* offsets;
-    int64_t n_seqs;
+    const uint32_t* qblk;      // first block of the query set's packed buffer
+    const PackedHeader* qhdr;  // its header
+    const int64_t* q_offsets;
+    int64_t n_q;
+    const uint32_t* rblk;      // the same for the reference set (may alias the query set)
+    const PackedHeader* rhdr;
+    const int64_t* r_offsets;
+    int64_t n_r;
     const int32_t* pairs;
     int64_t n_pairs;
     sw_result* out;

@@ -209,3 +209,24 @@ def test_maximum_length_pairs(sw):
     ps = P.PairSet(np.concatenate(seqs), offs, np.array([[0, 1], [1, 0], [0, 2], [2, 0]], np.int32), "max")
     say("maximum length pairs")
     assert_same(gpu_align(sw, ps), expect(ps), ps, "max length")
+
+
+def test_two_sets_match_one_set(sw):
+    import torch
+    ps = P.config_small(300)
+    # queries = even sequences, references = odd sequences, in separate buffers
+    L = ps.lengths()
+    q_idx, r_idx = np.arange(0, ps.n_seqs, 2), np.arange(1, ps.n_seqs, 2)
+
+    def take(ix):
+        o = np.concatenate([[0], np.cumsum(L[ix])])
+        return ps.ascii[P.gather_segments(ps.offsets[ix], L[ix])], o
+
+    qa, qo = take(q_idx)
+    ra, ro = take(r_idx)
+    rng = np.random.default_rng(4)
+    pairs = np.stack([rng.integers(0, len(q_idx), 500), rng.integers(0, len(r_idx), 500)], 1).astype(np.int32)
+    qb, rb = sw.Batch(qa, qo), sw.Batch(ra, ro)
+    got = sw.align_sets(qb.packed, qb.offsets, rb.packed, rb.offsets, torch.from_numpy(pairs).cuda()).cpu().numpy()
+    one = P.PairSet(ps.ascii, ps.offsets, np.stack([q_idx[pairs[:, 0]], r_idx[pairs[:, 1]]], 1).astype(np.int32))
+    assert_same(got, expect(one), one, "two sets")

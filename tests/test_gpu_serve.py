@@ -1,0 +1,94 @@
+"""GPU serving: every request's results equal the oracle and are the same
+alone and when served concurrently with others; admission by slots and HBM
+budget."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import proteins as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2303_01845_amd as sw
+    from paper_2303_01845_amd.serve import Server, run_open_loop
+    w = P.serving(n_fam=300, per_fam=50, n_batches=24, max_batch=400, seed=1)
+    refs = sw.Batch(w.ref_ascii, w.ref_offsets)
+    return sw, Server, run_open_loop, w, refs
+
+
+def oracle_for(w, q, qo, cand):
+    # one pair set: queries first, then the whole reference set
+    asc = np.concatenate([q, w.ref_ascii])
+    offs = np.concatenate([qo, w.ref_offsets[1:] + qo[-1]])
+    pairs = cand.copy()
+    pairs[:, 1] += len(qo) - 1
+    return oracle.batch_ascii(asc, offs, pairs, 11, 1)
+
+
+def test_requests_alone_and_mixed(setup):
+    import torch
+    sw, Server, run_open_loop, w, refs = setup
+    srv = Server(refs.packed, refs.offsets, hbm_budget=1 << 30, max_slots=4)
+    try:
+        alone = []
+        for k, (q, qo, cand) in enumerate(w.batches):
+            t = srv.submit(q, qo, cand)
+            assert t is not None
+            alone.append(srv.wait(t))
+        say("alone done")
+        for k, (q, qo, cand) in enumerate(w.batches):
+            exp = oracle_for(w, q, qo, cand)
+            assert (alone[k] == exp).all(), "request %d differs from the oracle" % k
+        rng = np.random.default_rng(0)
+        arrivals = np.cumsum(rng.exponential(0.0005, len(w.batches)))
+        rec = run_open_loop(srv, w.batches, arrivals)
+        say("mixed done")
+        for k, r in enumerate(rec):
+            assert (r["result"] == alone[k]).all(), "request %d differs in the mix" % k
+        assert max(r["submit"] for r in rec) > 0
+    finally:
+        srv.close()
+
+
+def test_admission_limits(setup):
+    sw, Server, run_open_loop, w, refs = setup
+    q, qo, cand = max(w.batches, key=lambda b: len(b[2]))
+    need = Server.request_bytes(len(q), len(qo) - 1, len(cand))
+    srv = Server(refs.packed, refs.offsets, hbm_budget=need + need // 2, max_slots=4)
+    try:
+        t1 = srv.submit(q, qo, cand)
+        assert t1 is not None
+        assert srv.submit(q, qo, cand) is None          # budget: the second does not fit now
+        assert srv.stats()["inflight"] == 1
+        srv.wait(t1)
+        t2 = srv.submit(q, qo, cand)                     # memory freed: admitted
+        assert t2 is not None
+        srv.wait(t2)
+        assert srv.stats()["bytes_in_use"] == 0
+    finally:
+        srv.close()
+    tiny = Server(refs.packed, refs.offsets, hbm_budget=1024, max_slots=1)
+    try:
+        with pytest.raises(sw.SwError) as e:
+            tiny.submit(q, qo, cand)
+        assert e.value.status == sw.SW_ENOMEM
+    finally:
+        tiny.close()
+    one = Server(refs.packed, refs.offsets, hbm_budget=1 << 30, max_slots=1)
+    try:
+        t = one.submit(q, qo, cand)
+        assert one.submit(q, qo, cand) is None           # single slot busy
+        one.wait(t)
+    finally:
+        one.close()

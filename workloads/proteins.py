@@ -376,3 +376,71 @@ def config_block(n_fam: int = 2000, n_members: int = 100_000) -> PairSet:
     ps = PairSet(np.concatenate([qa, ra]), offs2,
                  np.stack([qq, rr + nq], 1).astype(np.int32), "block-%dx%d" % (nq, len(r_idx)))
     return ps
+
+
+# --------------------------------------------------------------------------
+# Serving workload
+# --------------------------------------------------------------------------
+
+class KmerIndex:
+    """Sorted (k-mer, reference) list of the distinct exact k-mers of a set."""
+
+    def __init__(self, asc, offs, k: int = 6):
+        km, seq = kmer_sets(asc, offs, k)
+        o = np.argsort(km, kind="stable")
+        self.km, self.seq, self.k, self.n = km[o], seq[o], k, len(offs) - 1
+
+    def candidates(self, q_asc, q_offs, min_shared: int = 2, top: int = 200):
+        """(query, reference, shared) with >= min_shared distinct shared k-mers,
+        at most `top` references per query (most shared first)."""
+        qk, qs = kmer_sets(q_asc, q_offs, self.k)
+        lo = np.searchsorted(self.km, qk, side="left")
+        hi = np.searchsorted(self.km, qk, side="right")
+        cnt = hi - lo
+        qrep = np.repeat(qs, cnt)
+        idx = np.repeat(lo - np.cumsum(cnt) + cnt, cnt) + np.arange(int(cnt.sum()))
+        key, shared = np.unique(qrep * self.n + self.seq[idx], return_counts=True)
+        keep = shared >= min_shared
+        key, shared = key[keep], shared[keep]
+        qq, rr = key // self.n, key % self.n
+        o = np.lexsort((rr, -shared, qq))
+        qq, rr, shared = qq[o], rr[o], shared[o]
+        rank = np.arange(len(qq)) - np.searchsorted(qq, qq, side="left")
+        m = rank < top
+        return qq[m], rr[m], shared[m]
+
+
+@dataclasses.dataclass
+class ServeWorkload:
+    ref_ascii: np.ndarray
+    ref_offsets: np.ndarray
+    batches: list          # (q_ascii uint8, q_offsets int64, cand int32 [n, 2])
+    sizes: np.ndarray      # queries per batch
+
+
+def serving(n_fam: int = 20000, per_fam: int = 50, n_batches: int = 200, max_batch: int = 10000,
+            top: int = 200, seed: int = 0, workers: int | None = None) -> ServeWorkload:
+    """Reference set: n_fam families x per_fam members (ancestors LN(280, 0.6)
+    clipped 30-5000, members Mutation(ancestor, U(0.2, 0.6), 0.03)).  Query
+    batches: sizes log-uniform on [1, max_batch]; each query a fresh member of
+    a random family; candidates: references sharing >= 2 distinct exact 6-mers,
+    the `top` most-shared first."""
+    rng = rng_for(5, seed)
+    La = lognormal_lengths(rng, n_fam, 280.0, 0.6, 30, 5000)
+    anc, anc_o = _from_lengths(rng, La)
+    fam = np.repeat(np.arange(n_fam), per_fam)
+    src = anc[gather_segments(anc_o[fam], La[fam])]
+    src_o = np.concatenate([[0], np.cumsum(La[fam])])
+    ref, ref_o = mutate_many(rng, src, src_o, rng.uniform(0.2, 0.6, len(fam)), 0.03)
+    index = KmerIndex(ref, ref_o)
+    sizes = np.exp(rng.uniform(0.0, np.log(max_batch + 1), n_batches)).astype(np.int64).clip(1, max_batch)
+    batches = []
+    for b in range(n_batches):
+        r2 = rng_for(6, seed * 100003 + b)
+        f = r2.integers(0, n_fam, int(sizes[b]))
+        s2 = anc[gather_segments(anc_o[f], La[f])]
+        s2o = np.concatenate([[0], np.cumsum(La[f])])
+        q, qo = mutate_many(r2, s2, s2o, r2.uniform(0.2, 0.6, len(f)), 0.03)
+        qq, rr, _ = index.candidates(q, qo, 2, top)
+        batches.append((q, qo, np.stack([qq, rr], 1).astype(np.int32)))
+    return ServeWorkload(ref, ref_o, batches, sizes)
