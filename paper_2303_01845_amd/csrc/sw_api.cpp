@@ -37,7 +37,7 @@ struct Ordering {
     // plain buckets: [rank_begin, rank_end) and whether they hold long pairs
     struct Bucket {
         int rank_begin, rank_end;
-        bool wave;
+        bool wide;
     };
     std::vector<Bucket> buckets;
 };
@@ -53,7 +53,7 @@ Ordering make_ordering(int R, int inter_max)
 {
     struct Key {
         int cell;
-        bool wave;
+        bool wide;
         int bucket;
         int64_t cost;
         int s, c;
@@ -65,7 +65,7 @@ Ordering make_ordering(int R, int inter_max)
         for (int c = 1; c <= kMaxInterChunks; ++c) {
             Key k;
             k.cell = (s - 1) * kMaxInterChunks + (c - 1);
-            k.wave = false;
+            k.wide = false;
             k.bucket = ceil_log2(std::max<int64_t>((int64_t)s * R, 8 * c));
             const bool reachable = s <= smax && c <= cmax;
             k.cost = reachable ? (int64_t)s * c : -1;
@@ -74,10 +74,10 @@ Ordering make_ordering(int R, int inter_max)
             keys.push_back(k);
         }
     for (int b = 0; b < kNumLenBuckets; ++b)
-        for (int cb = 0; cb < kWaveCostBins; ++cb) {
+        for (int cb = 0; cb < kWideCostBins; ++cb) {
             Key k;
-            k.cell = kInterCells + b * kWaveCostBins + cb;
-            k.wave = true;
+            k.cell = kInterCells + b * kWideCostBins + cb;
+            k.wide = true;
             k.bucket = b;
             k.cost = cb;
             k.s = k.c = 0;
@@ -88,7 +88,7 @@ Ordering make_ordering(int R, int inter_max)
     // (longest-processing-time-first order for the device work queue)
     std::vector<Key> p = keys;
     std::stable_sort(p.begin(), p.end(), [](const Key& x, const Key& y) {
-        if (x.wave != y.wave) return x.wave;
+        if (x.wide != y.wide) return x.wide;
         if (x.cost != y.cost) return x.cost > y.cost;
         if (x.bucket != y.bucket) return x.bucket > y.bucket;
         return x.s > y.s;
@@ -98,15 +98,15 @@ Ordering make_ordering(int R, int inter_max)
     // bucket by decreasing cost
     std::vector<Key> q = keys;
     std::stable_sort(q.begin(), q.end(), [](const Key& x, const Key& y) {
-        if (x.wave != y.wave) return !x.wave;
+        if (x.wide != y.wide) return !x.wide;
         if (x.bucket != y.bucket) return x.bucket < y.bucket;
         if (x.cost != y.cost) return x.cost > y.cost;
         return x.s > y.s;
     });
     for (size_t r = 0; r < q.size(); ++r) {
         o.rank_cell_plain.push_back(q[r].cell);
-        if (r == 0 || q[r].wave != q[r - 1].wave || q[r].bucket != q[r - 1].bucket)
-            o.buckets.push_back({(int)r, (int)r + 1, q[r].wave});
+        if (r == 0 || q[r].wide != q[r - 1].wide || q[r].bucket != q[r - 1].bucket)
+            o.buckets.push_back({(int)r, (int)r + 1, q[r].wide});
         else
             o.buckets.back().rank_end = (int)r + 1;
     }
@@ -125,12 +125,13 @@ struct GraphKey {
     int32_t go, ge;
     void* out;
     int R, inter_max, grid;
+    int64_t slot_words;
     bool operator<(const GraphKey& o) const
     {
         return std::tie(q_packed, q_offsets, n_q, r_packed, r_offsets, n_r, pairs, n_pairs, go, ge, out, R,
-                        inter_max, grid) < std::tie(o.q_packed, o.q_offsets, o.n_q, o.r_packed, o.r_offsets,
-                                                    o.n_r, o.pairs, o.n_pairs, o.go, o.ge, o.out, o.R,
-                                                    o.inter_max, o.grid);
+                        inter_max, grid, slot_words) <
+               std::tie(o.q_packed, o.q_offsets, o.n_q, o.r_packed, o.r_offsets, o.n_r, o.pairs, o.n_pairs, o.go,
+                        o.ge, o.out, o.R, o.inter_max, o.grid, o.slot_words);
     }
 };
 
@@ -240,7 +241,7 @@ int grow(T** p, int64_t count)
     return SW_OK;
 }
 
-int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, int grid, Workspace** out)
+int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, Workspace** out)
 {
     auto& slot = d.ws[stream];
     if (!slot) slot.reset(new Workspace());
@@ -261,18 +262,26 @@ int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, int grid, Work
         w.pair_cap = cap;
         changed = true;
     }
-    const int64_t need = (int64_t)grid * slot_words(d.R, d.inter_max);
-    if (need > w.scratch_words) {
-        int rc = grow(&w.scratch, need);
-        if (rc) return rc;
-        w.scratch_words = need;
-        changed = true;
-    }
     if (changed) {
         for (auto& g : w.graphs) (void)hipGraphExecDestroy(g.second);
         w.graphs.clear();
     }
     *out = &w;
+    return SW_OK;
+}
+
+// Scratch slots for `grid` blocks of `words` each (never shrinks).
+int ensure_scratch(Workspace& w, int64_t need)
+{
+    if (need <= w.scratch_words) return SW_OK;
+    int rc = grow(&w.scratch, need);
+    if (rc) {
+        w.scratch_words = 0;
+        return rc;
+    }
+    w.scratch_words = need;
+    for (auto& g : w.graphs) (void)hipGraphExecDestroy(g.second);
+    w.graphs.clear();
     return SW_OK;
 }
 
@@ -336,8 +345,18 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     Device& d = *dp;
     const int grid = d.n_cu * blocks_per_cu(d);
     Workspace* wp = nullptr;
-    if ((rc = get_workspace(d, stream, n_pairs, grid, &wp))) return rc;
+    if ((rc = get_workspace(d, stream, n_pairs, &wp))) return rc;
     Workspace& w = *wp;
+    // the boundary slots hold one cell per reference column: size them for the
+    // longest reference of this call (one small reduction and a sync)
+    HIP_TRY(launch_max_len(r_offsets_dev, n_r, w.counters + kCntMaxLen, stream), "max length");
+    HIP_TRY(hipMemcpyAsync(w.host_rank_start, w.counters + kCntMaxLen, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           stream),
+            "max length readback");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const int max_ref = std::max(0, (int)w.host_rank_start[0]);
+    const int64_t sw_words = slot_words(d.inter_max, max_ref);
+    if ((rc = ensure_scratch(w, (int64_t)grid * sw_words))) return rc;
 
     Args a;
     std::memset(&a, 0, sizeof(a));
@@ -359,7 +378,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     a.counters = w.counters;
     a.err = d.err;
     a.scratch = w.scratch;
-    a.slot_words = slot_words(d.R, d.inter_max);
+    a.slot_words = sw_words;
     a.go = scoring->gap_open;
     a.ge = scoring->gap_extend;
     a.rows_per_lane = d.R;
@@ -376,8 +395,8 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             const int first = w.host_rank_start[b.rank_begin];
             const int count = w.host_rank_start[b.rank_end] - first;
             if (count <= 0) continue;
-            const int items = b.wave ? count : (count + kWave - 1) / kWave;
-            HIP_TRY(launch_plain(a, b.wave, first, count, std::min(items, grid), stream), "plain launch");
+            const int items = (count + kWave - 1) / kWave;
+            HIP_TRY(launch_plain(a, b.wide, first, count, std::min(items, grid), stream), "plain launch");
         }
     } else {
         a.rank_cell = d.rank_cell_persistent;
@@ -386,7 +405,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             HIP_TRY(launch_persistent(a, grid, stream), "persistent launch");
         } else {
             GraphKey key{q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev,
-                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, grid};
+                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, grid, sw_words};
             auto it = w.graphs.find(key);
             if (it == w.graphs.end()) {
                 if (w.graphs.size() >= 16) {

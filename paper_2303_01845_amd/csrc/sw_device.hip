@@ -18,15 +18,13 @@
 // Keeping E and F saturated at 0 leaves H exactly as in the textbook
 // recurrence: by induction E_sat = max(E, 0), and H only uses max(0, E).
 //
-// Two kernel bodies:
-//  * lane-per-pair ("inter"): each lane aligns its own pair; the lane keeps R
-//    query rows in registers and sweeps the reference; horizontal strips of R
-//    rows hand their bottom row to the next strip through a per-block scratch
-//    slot; the substitution scores come from a per-lane query profile in LDS.
-//  * wave-per-pair ("wavefront"): the 64 lanes of a wave split a 64R-row strip,
-//    lane l owning rows [lR, lR+R); at step t lane l computes column t - l, and
-//    the bottom H and F of lane l-1 (its previous step) arrive by DPP
-//    wave_shr:1.  Strips hand over their bottom row through the scratch slot.
+// Kernel body: one pair per lane.  The lane keeps R query rows in registers
+// and sweeps the reference; horizontal strips of R rows hand their bottom row
+// to the next strip through a per-block scratch slot; the substitution scores
+// come from a per-lane query profile in LDS.  Two variants: "narrow" for
+// pairs whose scores fit 16 bits (one dword per boundary cell, 16-bit column
+// tags) and "wide" for any pair up to the length limit (two dwords per
+// boundary cell, 12-bit column tags folded every 4096 columns).
 
 #include <algorithm>
 
@@ -208,6 +206,7 @@ __device__ __forceinline__ void build_profile(uint8_t* prof, int lane, const uin
         sel[w][2] = s2;
     }
     uint8_t* base = prof + lane * R;
+#pragma unroll 1
     for (int c = 0; c < kNumSym; ++c) {
         const uint32_t* t = c_tables.tab[c];
         const uint32_t t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3], t4 = t[4], t5 = t[5];
@@ -330,11 +329,14 @@ struct Best {
 // query position Q0 + i (REV: Q0 - i), column j reads reference position
 // R0 + j (REV: R0 - j).  Forward: returns the best score and its first cell.
 // REV: stops a lane after the first strip whose rows reach `target`.
-// Scratch slot layout: [chunk][lane][8 columns] of (H | F << 16).
-template <int R, bool REV>
+// Scratch slot layout: [chunk][lane][8 columns] of (H | F << 16) (narrow) or
+// of (H, F) pairs (wide).
+template <int R, bool REV, bool WIDE>
 __device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__ slot, int64_t Q0, int M,
                             int64_t R0, int N, int target)
 {
+    constexpr int TB = WIDE ? 12 : 16;  // tag bits of the per-row trackers
+    constexpr int SW = WIDE ? 4 : 2;    // uint4 per lane per chunk in the slot
     const int lane = threadIdx.x & (kWave - 1);
     const uint8_t* prof_lane = prof + lane * R;
     const uint32_t go = (uint32_t)a.go;
@@ -347,8 +349,9 @@ __device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__
     bool done = my_strips == 0 || (REV && target <= 0);
     const SeqView qv = seq_view(a.qblk, Q0);
     const SeqView rv = seq_view(a.rblk, R0);
-    uint4* slot4 = reinterpret_cast<uint4*>(slot) + 2 * lane;
+    uint4* slot4 = reinterpret_cast<uint4*>(slot) + SW * lane;
 
+#pragma unroll 1
     for (int s = 0; s < ws; ++s) {
         if (__ballot(!done && s < my_strips) == 0) break;
         const bool act = !done && s < my_strips;
@@ -369,24 +372,41 @@ __device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__
         int hdiag = 0;
         const bool read_top = s > 0;  // uniform
 
+        // wide: fold the 4096-column trackers into (score, row, column) with
+        // score descending, then row, then column ascending
+        auto fold = [&](int jbase) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int sc = (int)(K[r] >> 12);
+                const int row = row0 + r;
+                if (act && row < M && sc > 0 && (sc > b.s || (sc == b.s && row < b.i))) {
+                    b.s = sc;
+                    b.i = row;
+                    b.j = jbase + 4095 - (int)(K[r] & 4095u);
+                }
+                K[r] = 0;
+            }
+        };
+
         // chunk c covers columns 8c .. 8c+7; a lane past its last column reads
         // position 0 and masks everything to the pad code
         auto chunk_x = [&](int c) -> int { return 8 * c >= N ? 0 : (REV ? -8 * c - 7 : 8 * c); };
         uint32_t nw_n, hw_n;
         window8(rv, chunk_x(0), nw_n, hw_n);
-        uint4 t0_n = make_uint4(0, 0, 0, 0), t1_n = make_uint4(0, 0, 0, 0);
-        if (read_top) {
-            t0_n = slot4[0];
-            t1_n = slot4[1];
-        }
+        uint4 t_n[SW];
+#pragma unroll
+        for (int w = 0; w < SW; ++w) t_n[w] = read_top ? slot4[w] : make_uint4(0, 0, 0, 0);
+#pragma unroll 1
         for (int c = 0; c < wc; ++c) {
             uint32_t nw = nw_n, hw = hw_n;
-            const uint4 t0 = t0_n, t1 = t1_n;
+            uint4 tc[SW];
+#pragma unroll
+            for (int w = 0; w < SW; ++w) tc[w] = t_n[w];
             const int cn = min(c + 1, wc - 1);
             window8(rv, chunk_x(cn), nw_n, hw_n);
             if (read_top) {
-                t0_n = slot4[cn * 2 * kWave];
-                t1_n = slot4[cn * 2 * kWave + 1];
+#pragma unroll
+                for (int w = 0; w < SW; ++w) t_n[w] = slot4[cn * SW * kWave + w];
             }
             const int valid = min(max(N - 8 * c, 0), 8);
             if (valid < 8) {
@@ -400,28 +420,54 @@ __device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__
                     hw |= (0xFFu << valid) & 0xFFu;
                 }
             }
-            const uint32_t top[8] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
-            uint32_t bot[8];
+            uint32_t top[4 * SW], bot[4 * SW];
+#pragma unroll
+            for (int w = 0; w < SW; ++w) {
+                top[4 * w] = tc[w].x;
+                top[4 * w + 1] = tc[w].y;
+                top[4 * w + 2] = tc[w].z;
+                top[4 * w + 3] = tc[w].w;
+            }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int nb = REV ? 7 - k : k;
                 const uint32_t code = ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
                 uint32_t w[R / 4];
                 load_profile<R>(prof_lane, code, w);
-                const int htop = (int)(top[k] & 0xFFFFu);
-                int F = (int)(top[k] >> 16);
-                const uint32_t tag = (uint32_t)uni(0xFFFF - (8 * c + k));
-                column_step<R, 16>(H, E, K, w, hdiag, F, tag, go, ge);
+                const int j = 8 * c + k;
+                int htop, F;
+                uint32_t tag;
+                if constexpr (WIDE) {
+                    htop = (int)top[2 * k];
+                    F = (int)top[2 * k + 1];
+                    tag = (uint32_t)uni(4095 - (j & 4095));
+                } else {
+                    htop = (int)(top[k] & 0xFFFFu);
+                    F = (int)(top[k] >> 16);
+                    tag = (uint32_t)uni(0xFFFF - j);
+                }
+                column_step<R, TB>(H, E, K, w, hdiag, F, tag, go, ge);
                 hdiag = htop;
-                bot[k] = (uint32_t)H[R - 1] | ((uint32_t)F << 16);
+                if constexpr (WIDE) {
+                    bot[2 * k] = (uint32_t)H[R - 1];
+                    bot[2 * k + 1] = (uint32_t)F;
+                } else {
+                    bot[k] = (uint32_t)H[R - 1] | ((uint32_t)F << 16);
+                }
             }
             // every lane writes its own slot region; a lane without a next
             // strip never reads it back before overwriting it
-            slot4[c * 2 * kWave] = make_uint4(bot[0], bot[1], bot[2], bot[3]);
-            slot4[c * 2 * kWave + 1] = make_uint4(bot[4], bot[5], bot[6], bot[7]);
+#pragma unroll
+            for (int w = 0; w < SW; ++w)
+                slot4[c * SW * kWave + w] = make_uint4(bot[4 * w], bot[4 * w + 1], bot[4 * w + 2], bot[4 * w + 3]);
+            if constexpr (WIDE) {
+                if (((8 * c + 7) & 4095) == 4095) fold(8 * c + 7 - 4095);
+            }
         }
         block_fence();
-        if (act) {
+        if constexpr (WIDE) {
+            fold((8 * wc - 1) & ~4095);
+        } else if (act) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int sc = (int)(K[r] >> 16);
@@ -431,129 +477,8 @@ __device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__
                     b.j = (int)(0xFFFFu - (K[r] & 0xFFFFu));
                 }
             }
-            if (REV && b.s >= target) done = true;
         }
-    }
-    return b;
-}
-
-// ------------------------------------------------------------------ wave-per-pair sweep
-// One pair per wave.  Strip s covers rows [64Rs, 64R(s+1)); lane l owns rows
-// 64Rs + lR + [0, R).  Scratch slot: int2 (H, F) per column, the bottom row of
-// the previous strip.  Tags cover 4096 steps; trackers are folded into
-// (score, step) per row every 4096 steps.
-template <int R, bool REV>
-__device__ Best wave_sweep(const Args& a, uint8_t* prof, int2* __restrict__ slot, int64_t Q0, int M,
-                           int64_t R0, int N, int target)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    Q0 = uni64(Q0);
-    R0 = uni64(R0);
-    M = uni(M);
-    N = uni(N);
-    target = uni(target);
-    const uint8_t* prof_lane = prof + lane * R;
-    const uint32_t go = (uint32_t)a.go;
-    const int ge = a.ge;
-    Best b{0, -1, -1};
-    if (M <= 0 || N <= 0 || (REV && target <= 0)) return b;
-    constexpr int kRowsPerStrip = kWave * R;
-    const int nstrips = (M + kRowsPerStrip - 1) / kRowsPerStrip;
-    const SeqView qv = seq_view(a.qblk, Q0);
-    const SeqView rv = seq_view(a.rblk, R0);
-
-    for (int s = 0; s < nstrips; ++s) {
-        const int rows_left = M - s * kRowsPerStrip;
-        const int L = min(kWave, (rows_left + R - 1) / R);  // lanes holding at least one row
-        const int row0 = s * kRowsPerStrip + lane * R;
-        {
-            uint32_t qc[R];
-            row_codes<R, REV>(qv, row0, M, qc);
-            build_profile<R>(prof, lane, qc);
-        }
-        int H[R], E[R];
-        uint32_t K[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            H[r] = 0;
-            E[r] = 0;
-            K[r] = 0;
-        }
-        // this lane's best (score desc, row asc, column asc) over folded blocks
-        int ls = 0, li = -1, lj = -1;
-        int hdiag = 0, hbot = 0, fbel = 0;
-        int ccode = kPadCode;
-        int in_code = kPadCode, in_h = 0, in_f = 0;  // lane k: column t + k of this 64-step block
-        int out_h = 0, out_f = 0;                    // lane k: bottom of column cb - 63 + k
-        const bool read_top = s > 0;
-        const bool write_bot = s + 1 < nstrips;      // then L == 64
-        const int T = N + L - 1;
-        // Fold the 4096-step trackers: a row's earlier block wins ties (strict
-        // '>'), a smaller row wins ties against a larger one.
-        auto fold = [&](int tbase) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int sc = (int)(K[r] >> 12);
-                const int row = row0 + r;
-                if (row < M && sc > 0 && (sc > ls || (sc == ls && row < li))) {
-                    ls = sc;
-                    li = row;
-                    lj = tbase + 4095 - (int)(K[r] & 4095u) - lane;
-                }
-                K[r] = 0;
-            }
-        };
-        for (int t = 0; t < T; ++t) {
-            if ((t & 63) == 0) {
-                const int col = t + lane;
-                in_code = col < N ? (int)code_at(rv, REV ? -col : col) : kPadCode;
-                if (read_top && col < N) {
-                    const int2 v = slot[col];
-                    in_h = v.x;
-                    in_f = v.y;
-                } else {
-                    in_h = 0;
-                    in_f = 0;
-                }
-            }
-            ccode = dpp_mov<kWaveShr1>(in_code, ccode);
-            const int htop = dpp_mov<kWaveShr1>(in_h, hbot);
-            const int ftop = dpp_mov<kWaveShr1>(in_f, fbel);
-            in_code = dpp_mov<kWaveShl1>(in_code, in_code);
-            in_h = dpp_mov<kWaveShl1>(in_h, in_h);
-            in_f = dpp_mov<kWaveShl1>(in_f, in_f);
-            const int j = t - lane;
-            if (j >= 0 && j < N && lane < L) {
-                uint32_t w[R / 4];
-                load_profile<R>(prof_lane, (uint32_t)ccode, w);
-                int F = ftop;
-                column_step<R, 12>(H, E, K, w, hdiag, F, (uint32_t)uni(4095 - (t & 4095)), go, ge);
-                hdiag = htop;
-                hbot = H[R - 1];
-                fbel = F;
-            }
-            if (write_bot) {
-                const int cb = t - (kWave - 1);  // column finished by lane 63 at this step
-                out_h = dpp_mov<kWaveShl1>(hbot, out_h);
-                out_f = dpp_mov<kWaveShl1>(fbel, out_f);
-                if (cb >= 0 && ((cb & 63) == 63 || cb == N - 1)) {
-                    const int col = cb - 63 + lane;
-                    if (col >= (cb & ~63)) slot[col] = make_int2(out_h, out_f);
-                }
-            }
-            if ((t & 4095) == 4095) fold(t & ~4095);
-        }
-        fold((T - 1) & ~4095);
-        block_fence();
-        const int smax = uni(wave_max(ls));
-        if (smax > b.s) {
-            const uint64_t m = __ballot(ls == smax);
-            const int wl = __ffsll((unsigned long long)m) - 1;
-            b.s = smax;
-            b.i = __builtin_amdgcn_readlane(li, wl);
-            b.j = __builtin_amdgcn_readlane(lj, wl);
-        }
-        if (REV && b.s >= target) break;
+        if (REV && act && b.s >= target) done = true;
     }
     return b;
 }
@@ -575,7 +500,7 @@ __device__ __forceinline__ void write_result(sw_result* out, int pid, int S, int
     out[pid] = r;
 }
 
-template <int R>
+template <int R, bool WIDE>
 __device__ void do_inter_group(const Args& a, int first, int count, uint8_t* prof, uint32_t* slot)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -591,39 +516,30 @@ __device__ void do_inter_group(const Args& a, int first, int count, uint8_t* pro
         m = (int)(a.q_offsets[qi + 1] - qoff);
         roff = a.r_offsets[ri];
         n = (int)(a.r_offsets[ri + 1] - roff);
+        // the slot must hold one boundary cell per column of this pair
+        const int64_t need = (int64_t)((n + 7) / 8) * kWave * (WIDE ? 16 : 8);
+        if (need > a.slot_words) {
+            atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+            sw_result bad;
+            bad.score = bad.q_start = bad.q_end = bad.r_start = bad.r_end = -1;
+            a.out[pid] = bad;
+            pid = -1;
+            m = n = 0;
+        }
     }
-    const Best f = inter_sweep<R, false>(a, prof, slot, qoff, m, roff, n, 0);
+    const Best f = inter_sweep<R, false, WIDE>(a, prof, slot, qoff, m, roff, n, 0);
     const bool has = f.s > 0;
-    const Best r = inter_sweep<R, true>(a, prof, slot, qoff + (has ? f.i : 0), has ? f.i + 1 : 0,
-                                        roff + (has ? f.j : 0), has ? f.j + 1 : 0, f.s);
+    const Best r = inter_sweep<R, true, WIDE>(a, prof, slot, qoff + (has ? f.i : 0), has ? f.i + 1 : 0,
+                                              roff + (has ? f.j : 0), has ? f.j + 1 : 0, f.s);
     if (pid >= 0) {
         if (has && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
         write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
     }
 }
 
-template <int R>
-__device__ void do_wave_pair(const Args& a, int pid, uint8_t* prof, int2* slot)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    pid = uni(pid);
-    if (pid < 0 || pid >= a.n_pairs) {
-        if (lane == 0) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
-        return;
-    }
-    const int qi = uni(a.pairs[2 * pid]), ri = uni(a.pairs[2 * pid + 1]);
-    const int64_t qoff = uni64(a.q_offsets[qi]), roff = uni64(a.r_offsets[ri]);
-    const int m = uni((int)(a.q_offsets[qi + 1] - qoff)), n = uni((int)(a.r_offsets[ri + 1] - roff));
-    const Best f = wave_sweep<R, false>(a, prof, slot, qoff, m, roff, n, 0);
-    Best r{0, -1, -1};
-    if (f.s > 0) r = wave_sweep<R, true>(a, prof, slot, qoff + f.i, f.i + 1, roff + f.j, f.j + 1, f.s);
-    if (lane == 0) {
-        if (f.s > 0 && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
-        write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
-    }
-}
-
 // ------------------------------------------------------------------ kernels
+// Work items, in queue order: groups of up to 64 wide pairs, then groups of
+// up to 64 narrow pairs, each run by one wave, lane k taking pair k.
 template <int R>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_persistent(Args a)
 {
@@ -631,26 +547,27 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
     // the counters come from the scan; clamp them so that a bookkeeping error
     // can never index past the permutation
-    const int n_wave = min(max(a.counters[kCntWave], 0), (int)a.n_pairs);
-    const int n_inter = min(max(a.counters[kCntInter], 0), (int)a.n_pairs - n_wave);
+    const int n_wide = min(max(a.counters[kCntWide], 0), (int)a.n_pairs);
+    const int n_inter = min(max(a.counters[kCntInter], 0), (int)a.n_pairs - n_wide);
+    const int n_wgroups = (n_wide + kWave - 1) / kWave;
     const int n_groups = (n_inter + kWave - 1) / kWave;
-    const int total = n_wave + n_groups;
+    const int total = n_wgroups + n_groups;
     for (;;) {
         int item = 0;
         if ((threadIdx.x & (kWave - 1)) == 0) item = atomicAdd(&a.counters[kCntHead], 1);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total) break;
-        if (item < n_wave) {
-            do_wave_pair<R>(a, a.perm[item], lds, reinterpret_cast<int2*>(slot));
+        if (item < n_wgroups) {
+            do_inter_group<R, true>(a, item * kWave, min(kWave, n_wide - item * kWave), lds, slot);
         } else {
-            const int g = item - n_wave;
-            do_inter_group<R>(a, n_wave + g * kWave, min(kWave, n_inter - g * kWave), lds, slot);
+            const int g = item - n_wgroups;
+            do_inter_group<R, false>(a, n_wide + g * kWave, min(kWave, n_inter - g * kWave), lds, slot);
         }
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_plain_inter(Args a, int first, int count)
+template <int R, bool WIDE>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_plain(Args a, int first, int count)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
@@ -658,18 +575,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     count = min(count, (int)a.n_pairs - first);
     const int groups = (count + kWave - 1) / kWave;
     for (int g = blockIdx.x; g < groups; g += gridDim.x)
-        do_inter_group<R>(a, first + g * kWave, min(kWave, count - g * kWave), lds, slot);
+        do_inter_group<R, WIDE>(a, first + g * kWave, min(kWave, count - g * kWave), lds, slot);
 }
 
-template <int R>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_plain_wave(Args a, int first, int count)
+// Longest sequence of a set (for sizing the scratch slots).
+__global__ void k_max_len(const int64_t* __restrict__ offs, int64_t n, int32_t* out)
 {
-    extern __shared__ __align__(16) uint8_t lds[];
-    uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
-    first = max(first, 0);
-    count = min(count, (int)a.n_pairs - first);
-    for (int p = blockIdx.x; p < count; p += gridDim.x)
-        do_wave_pair<R>(a, a.perm[first + p], lds, reinterpret_cast<int2*>(slot));
+    int64_t best = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        best = max(best, offs[k + 1] - offs[k]);
+    best = min(best, (int64_t)0x7FFFFFFF);
+    if (best > 0) atomicMax(out, (int32_t)best);
 }
 
 // ASCII -> packed.  Thread t writes the 32 residues of high word t: positions
@@ -745,8 +661,14 @@ __device__ __forceinline__ int classify(const Args& a, int64_t k)
     const int64_t cost = m * n;
     const int msb = 63 - __clzll((unsigned long long)cost);
     const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15) : 0;
-    const int cb = min(kWaveCostBins - 1, 16 * msb + frac);
-    return kInterCells + ceil_log2(mx) * kWaveCostBins + cb;
+    const int cb = min(kWideCostBins - 1, 16 * msb + frac);
+    return kInterCells + ceil_log2(mx) * kWideCostBins + cb;
+}
+
+__global__ void k_fill(int32_t* p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 __global__ void k_zero_cells(Args a)
@@ -804,7 +726,7 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
     }
     if (t == 1023) {
         a.rank_start[kNumCells] = part[1023];
-        a.counters[kCntWave] = nw[1023];
+        a.counters[kCntWide] = nw[1023];
         a.counters[kCntInter] = part[1023] - nw[1023];
     }
 }
@@ -821,12 +743,11 @@ __global__ void k_scatter(Args a)
 // ------------------------------------------------------------------ launchers
 size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * R; }
 
-int64_t slot_words(int R, int inter_max_len)
+int64_t slot_words(int inter_max_len, int max_ref_len)
 {
-    (void)R;
-    const int64_t inter = (int64_t)((inter_max_len + 7) / 8) * kWave * 8;
-    const int64_t wave = (int64_t)(SW_MAX_SEQ_LEN + 1) * 2;
-    return inter > wave ? inter : wave;
+    const int64_t narrow = (int64_t)((inter_max_len + 7) / 8) * kWave * 8;
+    const int64_t wide = (int64_t)((std::min(max_ref_len, SW_MAX_SEQ_LEN) + 7) / 8) * kWave * 16;
+    return std::max<int64_t>(narrow, wide);
 }
 
 __global__ void k_pack_header(PackedHeader* h, int64_t n)
@@ -880,34 +801,41 @@ hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream)
 }
 
 template <int R>
-static hipError_t launch_plain_r(const Args& a, bool wave, int first, int count, int grid, hipStream_t stream)
+static hipError_t launch_plain_r(const Args& a, bool wide, int first, int count, int grid, hipStream_t stream)
 {
-    if (wave)
-        hipLaunchKernelGGL(k_plain_wave<R>, dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
+    if (wide)
+        hipLaunchKernelGGL((k_plain<R, true>), dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
     else
-        hipLaunchKernelGGL(k_plain_inter<R>, dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
+        hipLaunchKernelGGL((k_plain<R, false>), dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
     return hipGetLastError();
 }
 
-hipError_t launch_plain(const Args& a, bool wave, int first, int count, int grid, hipStream_t stream)
+hipError_t launch_plain(const Args& a, bool wide, int first, int count, int grid, hipStream_t stream)
 {
     switch (a.rows_per_lane) {
-    case 16: return launch_plain_r<16>(a, wave, first, count, grid, stream);
-    case 32: return launch_plain_r<32>(a, wave, first, count, grid, stream);
+    case 16: return launch_plain_r<16>(a, wide, first, count, grid, stream);
+    case 32: return launch_plain_r<32>(a, wide, first, count, grid, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
+hipError_t launch_max_len(const int64_t* offs, int64_t n, int32_t* out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, out, 1, 0);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_max_len, dim3((unsigned)blocks), dim3(256), 0, stream, offs, n, out);
+    return hipGetLastError();
+}
+
 hipError_t set_kernel_attributes()
 {
-    hipError_t e = hipSuccess;
     const int bytes32 = (int)lds_bytes(32);
-    e = hipFuncSetAttribute((const void*)k_persistent<32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
+    hipError_t e = hipFuncSetAttribute((const void*)k_persistent<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       bytes32);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_plain_inter<32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
+    e = hipFuncSetAttribute((const void*)k_plain<32, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_plain_wave<32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
-    return e;
+    return hipFuncSetAttribute((const void*)k_plain<32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
 }
 
 }  // namespace swk

@@ -44,17 +44,18 @@ constexpr int kWave = 64;
 constexpr int kMaxInterStrips = 64;    // ceil(inter_max_len / rows_per_lane) <= this
 constexpr int kMaxInterChunks = 128;   // ceil(inter_max_len / 8) <= this
 constexpr int kMaxInterLen = 1024;
-constexpr int kWaveCostBins = 512;     // floor(16 * log2(m*n)) for long pairs
+constexpr int kWideCostBins = 512;     // floor(16 * log2(m*n)) for long (wide) pairs
 constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
 constexpr int kInterCells = kMaxInterStrips * kMaxInterChunks;
-constexpr int kWaveCells = kNumLenBuckets * kWaveCostBins;
-constexpr int kNumCells = kInterCells + kWaveCells;
+constexpr int kWideCells = kNumLenBuckets * kWideCostBins;
+constexpr int kNumCells = kInterCells + kWideCells;
 
 // counters[] slots in the workspace
 enum {
     kCntHead = 0,   // persistent work-queue head
-    kCntWave = 1,   // number of long pairs (one wave each)
-    kCntInter = 2,  // number of lane-per-pair pairs
+    kCntWide = 1,   // number of long pairs (wide lane-per-pair variant)
+    kCntInter = 2,  // number of short pairs (narrow variant)
+    kCntMaxLen = 3, // longest reference sequence of the call
     kNumCounters = 16
 };
 enum { kErrRange = 1, kErrCode = 2, kErrInternal = 4 };
@@ -89,10 +90,11 @@ struct Args {
 hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err, hipStream_t stream);
 hipError_t launch_prepare(const Args& a, hipStream_t stream);  // zero, classify, scan, scatter
 hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream);
-hipError_t launch_plain(const Args& a, bool wave, int first, int count, int grid, hipStream_t stream);
+hipError_t launch_plain(const Args& a, bool wide, int first, int count, int grid, hipStream_t stream);
+hipError_t launch_max_len(const int64_t* offs, int64_t n, int32_t* out, hipStream_t stream);
 hipError_t set_kernel_attributes();
 size_t lds_bytes(int rows_per_lane);
-int64_t slot_words(int rows_per_lane, int inter_max_len);
+int64_t slot_words(int inter_max_len, int max_ref_len);
 void matrix_ncbi(int8_t out[kNumSym * kNumSym], char letters[kNumSym + 1]);
 const char* code_order();
 

@@ -117,8 +117,9 @@ def test_adversarial_short(sw, gaps):
     assert_same(gpu_align(sw, ps, *gaps), expect(ps, *gaps), ps, "adversarial %s" % (gaps,))
 
 
-def test_adversarial_long_wavefront(sw):
-    # every pair longer than the lane-per-pair limit: one wave per pair
+def test_adversarial_long_wide(sw):
+    # every pair longer than the short-pair limit: the wide variant (32-bit
+    # boundary cells, folded 12-bit column tags)
     ps = adversarial_set(7, 36, 3000)
     keep = [k for k in range(ps.n_pairs) if max(ps.lengths()[ps.pairs[k]]) > 1024]
     ps = ps.subset(keep)
