@@ -37,7 +37,7 @@ struct Ordering {
     // plain buckets: [rank_begin, rank_end) and whether they hold long pairs
     struct Bucket {
         int rank_begin, rank_end;
-        bool wide;
+        int kind;  // lanes per pair
     };
     std::vector<Bucket> buckets;
 };
@@ -53,7 +53,7 @@ Ordering make_ordering(int R, int inter_max)
 {
     struct Key {
         int cell;
-        bool wide;
+        int kind;  // lanes per pair: 64, 16 or 1
         int bucket;
         int64_t cost;
         int s, c;
@@ -65,7 +65,7 @@ Ordering make_ordering(int R, int inter_max)
         for (int c = 1; c <= kMaxInterChunks; ++c) {
             Key k;
             k.cell = (s - 1) * kMaxInterChunks + (c - 1);
-            k.wide = false;
+            k.kind = 1;
             k.bucket = ceil_log2(std::max<int64_t>((int64_t)s * R, 8 * c));
             const bool reachable = s <= smax && c <= cmax;
             k.cost = reachable ? (int64_t)s * c : -1;
@@ -77,7 +77,7 @@ Ordering make_ordering(int R, int inter_max)
         for (int cb = 0; cb < kWideCostBins; ++cb) {
             Key k;
             k.cell = kInterCells + b * kWideCostBins + cb;
-            k.wide = true;
+            k.kind = ((int64_t)1 << b) <= kMaxP16Len ? 16 : 64;
             k.bucket = b;
             k.cost = cb;
             k.s = k.c = 0;
@@ -88,7 +88,7 @@ Ordering make_ordering(int R, int inter_max)
     // (longest-processing-time-first order for the device work queue)
     std::vector<Key> p = keys;
     std::stable_sort(p.begin(), p.end(), [](const Key& x, const Key& y) {
-        if (x.wide != y.wide) return x.wide;
+        if (x.kind != y.kind) return x.kind > y.kind;
         if (x.cost != y.cost) return x.cost > y.cost;
         if (x.bucket != y.bucket) return x.bucket > y.bucket;
         return x.s > y.s;
@@ -98,15 +98,15 @@ Ordering make_ordering(int R, int inter_max)
     // bucket by decreasing cost
     std::vector<Key> q = keys;
     std::stable_sort(q.begin(), q.end(), [](const Key& x, const Key& y) {
-        if (x.wide != y.wide) return !x.wide;
+        if (x.kind != y.kind) return x.kind < y.kind;
         if (x.bucket != y.bucket) return x.bucket < y.bucket;
         if (x.cost != y.cost) return x.cost > y.cost;
         return x.s > y.s;
     });
     for (size_t r = 0; r < q.size(); ++r) {
         o.rank_cell_plain.push_back(q[r].cell);
-        if (r == 0 || q[r].wide != q[r - 1].wide || q[r].bucket != q[r - 1].bucket)
-            o.buckets.push_back({(int)r, (int)r + 1, q[r].wide});
+        if (r == 0 || q[r].kind != q[r - 1].kind || q[r].bucket != q[r - 1].bucket)
+            o.buckets.push_back({(int)r, (int)r + 1, q[r].kind});
         else
             o.buckets.back().rank_end = (int)r + 1;
     }
@@ -347,15 +347,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     Workspace* wp = nullptr;
     if ((rc = get_workspace(d, stream, n_pairs, &wp))) return rc;
     Workspace& w = *wp;
-    // the boundary slots hold one cell per reference column: size them for the
-    // longest reference of this call (one small reduction and a sync)
-    HIP_TRY(launch_max_len(r_offsets_dev, n_r, w.counters + kCntMaxLen, stream), "max length");
-    HIP_TRY(hipMemcpyAsync(w.host_rank_start, w.counters + kCntMaxLen, sizeof(int32_t), hipMemcpyDeviceToHost,
-                           stream),
-            "max length readback");
-    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    const int max_ref = std::max(0, (int)w.host_rank_start[0]);
-    const int64_t sw_words = slot_words(d.inter_max, max_ref);
+    const int64_t sw_words = slot_words();
     if ((rc = ensure_scratch(w, (int64_t)grid * sw_words))) return rc;
 
     Args a;
@@ -395,8 +387,9 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             const int first = w.host_rank_start[b.rank_begin];
             const int count = w.host_rank_start[b.rank_end] - first;
             if (count <= 0) continue;
-            const int items = (count + kWave - 1) / kWave;
-            HIP_TRY(launch_plain(a, b.wide, first, count, std::min(items, grid), stream), "plain launch");
+            const int per_item = kWave / b.kind;
+            const int items = (count + per_item - 1) / per_item;
+            HIP_TRY(launch_plain(a, b.kind, first, count, std::min(items, grid), stream), "plain launch");
         }
     } else {
         a.rank_cell = d.rank_cell_persistent;

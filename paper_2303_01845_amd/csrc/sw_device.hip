@@ -324,41 +324,66 @@ struct Best {
     int s, i, j;
 };
 
-// ------------------------------------------------------------------ lane-per-pair sweep
-// Each lane aligns rows [0, M) x columns [0, N) of its own pair.  Row i reads
-// query position Q0 + i (REV: Q0 - i), column j reads reference position
-// R0 + j (REV: R0 - j).  Forward: returns the best score and its first cell.
-// REV: stops a lane after the first strip whose rows reach `target`.
-// Scratch slot layout: [chunk][lane][8 columns] of (H | F << 16) (narrow) or
-// of (H, F) pairs (wide).
-template <int R, bool REV, bool WIDE>
-__device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__ slot, int64_t Q0, int M,
-                            int64_t R0, int N, int target)
+// ------------------------------------------------------------------ group sweep
+// A group of P lanes (P = 1, 16 or 64) aligns one pair: rows [0, M) x columns
+// [0, N).  Row i reads query position Q0 + i (REV: Q0 - i), column j reads
+// reference position R0 + j (REV: R0 - j).  Super-strip ss covers rows
+// [ss P R, (ss+1) P R); lane u of the group owns rows ss P R + u R + [0, R)
+// and at step t processes the 8-column chunk c = t - u.  The bottom row of
+// that chunk reaches lane u+1 through the LDS exchange buffer (written at the
+// end of step t, read at the start of step t+1 by the same wave, so no
+// barrier is needed); lane P-1 hands it to the next super-strip through the
+// block's scratch slot, laid out [chunk][group][8 columns].  Boundary cells
+// are (H | F << 16) in the narrow variant and (H, F) in the wide one.
+// Forward: the best score and its first cell.  REV: the group stops after the
+// first super-strip whose rows reach `target`.
+template <int P>
+__device__ __forceinline__ Best group_best(Best b)
+{
+#pragma unroll
+    for (int o = 1; o < P; o <<= 1) {
+        const int s = __shfl_xor(b.s, o, kWave), i = __shfl_xor(b.i, o, kWave), j = __shfl_xor(b.j, o, kWave);
+        if (s > b.s || (s == b.s && s > 0 && (i < b.i || (i == b.i && j < b.j)))) {
+            b.s = s;
+            b.i = i;
+            b.j = j;
+        }
+    }
+    return b;
+}
+
+template <int R, int P, bool REV, bool WIDE>
+__device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t* __restrict__ slot,
+                            int64_t Q0, int M, int64_t R0, int N, int target)
 {
     constexpr int TB = WIDE ? 12 : 16;  // tag bits of the per-row trackers
-    constexpr int SW = WIDE ? 4 : 2;    // uint4 per lane per chunk in the slot
+    constexpr int SW = WIDE ? 4 : 2;    // uint4 per boundary chunk of 8 columns
+    constexpr int G = kWave / P;        // groups per wave
     const int lane = threadIdx.x & (kWave - 1);
+    const int u = lane % P, g = lane / P;
     const uint8_t* prof_lane = prof + lane * R;
     const uint32_t go = (uint32_t)a.go;
     const int ge = a.ge;
-    Best b{0, -1, -1};
-    const int my_strips = (M > 0 && N > 0) ? (M + R - 1) / R : 0;
+    Best b{0, -1, -1};  // this lane's rows only
+    const int my_ss = (M > 0 && N > 0) ? (M + P * R - 1) / (P * R) : 0;
     const int my_chunks = (N + 7) / 8;
-    const int ws = uni(wave_max(my_strips));
-    const int wc = uni(wave_max(my_strips > 0 ? my_chunks : 0));
-    bool done = my_strips == 0 || (REV && target <= 0);
+    const int wss = uni(wave_max(my_ss));
+    const int wc = uni(wave_max(my_ss > 0 ? my_chunks : 0));
+    bool done = my_ss == 0 || (REV && target <= 0);
     const SeqView qv = seq_view(a.qblk, Q0);
     const SeqView rv = seq_view(a.rblk, R0);
-    uint4* slot4 = reinterpret_cast<uint4*>(slot) + SW * lane;
+    uint4* slot4 = reinterpret_cast<uint4*>(slot) + SW * g;
+    uint4* x_mine = xbuf + SW * lane;
+    const uint4* x_up = xbuf + SW * (lane > 0 ? lane - 1 : 0);
 
 #pragma unroll 1
-    for (int s = 0; s < ws; ++s) {
-        if (__ballot(!done && s < my_strips) == 0) break;
-        const bool act = !done && s < my_strips;
-        const int row0 = s * R;
+    for (int ss = 0; ss < wss; ++ss) {
+        if (__ballot(!done && ss < my_ss) == 0) break;
+        const bool gact = !done && ss < my_ss;
+        const int row0 = ss * P * R + u * R;
         {
             uint32_t qc[R];
-            row_codes<R, REV>(qv, act ? row0 : M, M, qc);
+            row_codes<R, REV>(qv, gact ? row0 : M, M, qc);
             build_profile<R>(prof, lane, qc);
         }
         int H[R], E[R];
@@ -370,117 +395,135 @@ __device__ Best inter_sweep(const Args& a, uint8_t* prof, uint32_t* __restrict__
             K[r] = 0;
         }
         int hdiag = 0;
-        const bool read_top = s > 0;  // uniform
+        const bool read_top = ss > 0;            // uniform
+        const bool write_next = ss + 1 < my_ss;  // uniform within the group
 
-        // wide: fold the 4096-column trackers into (score, row, column) with
-        // score descending, then row, then column ascending
-        auto fold = [&](int jbase) {
+        // wide: fold the 4096-column trackers into this lane's (score, row,
+        // column), score descending, then row, then column ascending.  Tags
+        // count steps: column = 8 t + k - 8 u.
+        auto fold = [&](int tcol_base) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int sc = (int)(K[r] >> 12);
                 const int row = row0 + r;
-                if (act && row < M && sc > 0 && (sc > b.s || (sc == b.s && row < b.i))) {
+                if (gact && row < M && sc > 0 && (sc > b.s || (sc == b.s && row < b.i))) {
                     b.s = sc;
                     b.i = row;
-                    b.j = jbase + 4095 - (int)(K[r] & 4095u);
+                    b.j = tcol_base + 4095 - (int)(K[r] & 4095u) - 8 * u;
                 }
                 K[r] = 0;
             }
         };
-
-        // chunk c covers columns 8c .. 8c+7; a lane past its last column reads
-        // position 0 and masks everything to the pad code
-        auto chunk_x = [&](int c) -> int { return 8 * c >= N ? 0 : (REV ? -8 * c - 7 : 8 * c); };
-        uint32_t nw_n, hw_n;
-        window8(rv, chunk_x(0), nw_n, hw_n);
-        uint4 t_n[SW];
-#pragma unroll
-        for (int w = 0; w < SW; ++w) t_n[w] = read_top ? slot4[w] : make_uint4(0, 0, 0, 0);
+        auto chunk_x = [&](int c) -> int {
+            return (c < 0 || 8 * c >= N) ? 0 : (REV ? -8 * c - 7 : 8 * c);
+        };
+        const int T = wc + P - 1;
 #pragma unroll 1
-        for (int c = 0; c < wc; ++c) {
-            uint32_t nw = nw_n, hw = hw_n;
+        for (int t = 0; t < T; ++t) {
+            const int c = t - u;
+            const bool act = gact && c >= 0 && c < my_chunks;
             uint4 tc[SW];
+            if (u == 0) {
+                // idle steps (before the first or past the last chunk) still
+                // read, so keep the index inside this pair's chunks
+                const int cc = min(max(c, 0), max(my_chunks - 1, 0));
 #pragma unroll
-            for (int w = 0; w < SW; ++w) tc[w] = t_n[w];
-            const int cn = min(c + 1, wc - 1);
-            window8(rv, chunk_x(cn), nw_n, hw_n);
-            if (read_top) {
+                for (int w = 0; w < SW; ++w)
+                    tc[w] = read_top ? slot4[cc * G * SW + w] : make_uint4(0, 0, 0, 0);
+            } else {
 #pragma unroll
-                for (int w = 0; w < SW; ++w) t_n[w] = slot4[cn * SW * kWave + w];
+                for (int w = 0; w < SW; ++w) tc[w] = x_up[w];
             }
-            const int valid = min(max(N - 8 * c, 0), 8);
-            if (valid < 8) {
-                if (REV) {
-                    const uint32_t m4 = valid == 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu >> (4 * valid));
-                    nw = (nw & ~m4) | (0x88888888u & m4);
-                    hw |= 0xFFu >> valid;
-                } else {
-                    const uint32_t m4 = valid == 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (4 * valid));
-                    nw = (nw & ~m4) | (0x88888888u & m4);
-                    hw |= (0xFFu << valid) & 0xFFu;
+            uint32_t nw, hw;
+            window8(rv, chunk_x(c), nw, hw);
+            uint32_t bot[4 * SW];
+#pragma unroll
+            for (int w = 0; w < 4 * SW; ++w) bot[w] = 0;
+            if (act) {
+                const int valid = min(N - 8 * c, 8);
+                if (valid < 8) {
+                    if (REV) {
+                        const uint32_t m4 = 0xFFFFFFFFu >> (4 * valid);
+                        nw = (nw & ~m4) | (0x88888888u & m4);
+                        hw |= 0xFFu >> valid;
+                    } else {
+                        const uint32_t m4 = 0xFFFFFFFFu << (4 * valid);
+                        nw = (nw & ~m4) | (0x88888888u & m4);
+                        hw |= (0xFFu << valid) & 0xFFu;
+                    }
+                }
+                uint32_t top[4 * SW];
+#pragma unroll
+                for (int w = 0; w < SW; ++w) {
+                    top[4 * w] = tc[w].x;
+                    top[4 * w + 1] = tc[w].y;
+                    top[4 * w + 2] = tc[w].z;
+                    top[4 * w + 3] = tc[w].w;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int nb = REV ? 7 - k : k;
+                    const uint32_t code = ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
+                    uint32_t w[R / 4];
+                    load_profile<R>(prof_lane, code, w);
+                    int htop, F;
+                    uint32_t tag;
+                    if constexpr (WIDE) {
+                        htop = (int)top[2 * k];
+                        F = (int)top[2 * k + 1];
+                        tag = (uint32_t)uni(4095 - ((8 * t + k) & 4095));
+                    } else {
+                        htop = (int)(top[k] & 0xFFFFu);
+                        F = (int)(top[k] >> 16);
+                        tag = (uint32_t)uni(0xFFFF - (8 * t + k));
+                    }
+                    column_step<R, TB>(H, E, K, w, hdiag, F, tag, go, ge);
+                    hdiag = htop;
+                    if constexpr (WIDE) {
+                        bot[2 * k] = (uint32_t)H[R - 1];
+                        bot[2 * k + 1] = (uint32_t)F;
+                    } else {
+                        bot[k] = (uint32_t)H[R - 1] | ((uint32_t)F << 16);
+                    }
                 }
             }
-            uint32_t top[4 * SW], bot[4 * SW];
+            // publish the bottom row of chunk c; lane u+1 reads it at the next
+            // step exactly when it processes chunk c, i.e. when this lane was
+            // active now
+            if constexpr (P > 1) {
 #pragma unroll
-            for (int w = 0; w < SW; ++w) {
-                top[4 * w] = tc[w].x;
-                top[4 * w + 1] = tc[w].y;
-                top[4 * w + 2] = tc[w].z;
-                top[4 * w + 3] = tc[w].w;
+                for (int w = 0; w < SW; ++w)
+                    x_mine[w] = make_uint4(bot[4 * w], bot[4 * w + 1], bot[4 * w + 2], bot[4 * w + 3]);
             }
+            if (u == P - 1 && act && write_next) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int nb = REV ? 7 - k : k;
-                const uint32_t code = ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
-                uint32_t w[R / 4];
-                load_profile<R>(prof_lane, code, w);
-                const int j = 8 * c + k;
-                int htop, F;
-                uint32_t tag;
-                if constexpr (WIDE) {
-                    htop = (int)top[2 * k];
-                    F = (int)top[2 * k + 1];
-                    tag = (uint32_t)uni(4095 - (j & 4095));
-                } else {
-                    htop = (int)(top[k] & 0xFFFFu);
-                    F = (int)(top[k] >> 16);
-                    tag = (uint32_t)uni(0xFFFF - j);
-                }
-                column_step<R, TB>(H, E, K, w, hdiag, F, tag, go, ge);
-                hdiag = htop;
-                if constexpr (WIDE) {
-                    bot[2 * k] = (uint32_t)H[R - 1];
-                    bot[2 * k + 1] = (uint32_t)F;
-                } else {
-                    bot[k] = (uint32_t)H[R - 1] | ((uint32_t)F << 16);
-                }
+                for (int w = 0; w < SW; ++w)
+                    slot4[c * G * SW + w] = make_uint4(bot[4 * w], bot[4 * w + 1], bot[4 * w + 2], bot[4 * w + 3]);
             }
-            // every lane writes its own slot region; a lane without a next
-            // strip never reads it back before overwriting it
-#pragma unroll
-            for (int w = 0; w < SW; ++w)
-                slot4[c * SW * kWave + w] = make_uint4(bot[4 * w], bot[4 * w + 1], bot[4 * w + 2], bot[4 * w + 3]);
             if constexpr (WIDE) {
-                if (((8 * c + 7) & 4095) == 4095) fold(8 * c + 7 - 4095);
+                if ((t & 511) == 511) fold(8 * t + 7 - 4095);
             }
         }
         block_fence();
         if constexpr (WIDE) {
-            fold((8 * wc - 1) & ~4095);
-        } else if (act) {
+            fold((8 * T - 1) & ~4095);
+        } else if (gact) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int sc = (int)(K[r] >> 16);
                 if (row0 + r < M && sc > b.s) {
                     b.s = sc;
                     b.i = row0 + r;
-                    b.j = (int)(0xFFFFu - (K[r] & 0xFFFFu));
+                    b.j = (int)(0xFFFFu - (K[r] & 0xFFFFu)) - 8 * u;
                 }
             }
         }
-        if (REV && act && b.s >= target) done = true;
+        if (REV) {
+            const Best gb = group_best<P>(b);
+            if (gact && gb.s >= target) done = true;
+        }
     }
-    return b;
+    return group_best<P>(b);
 }
 
 // ------------------------------------------------------------------ per-item drivers
@@ -500,14 +543,18 @@ __device__ __forceinline__ void write_result(sw_result* out, int pid, int S, int
     out[pid] = r;
 }
 
-template <int R, bool WIDE>
-__device__ void do_inter_group(const Args& a, int first, int count, uint8_t* prof, uint32_t* slot)
+// One work item: up to 64/P pairs, P lanes each.
+template <int R, int P, bool WIDE>
+__device__ void do_group(const Args& a, int first, int count, uint8_t* lds, uint32_t* slot)
 {
+    constexpr int G = kWave / P;
+    constexpr int SW = WIDE ? 4 : 2;
     const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / P, u = lane % P;
     int pid = -1, m = 0, n = 0;
     int64_t qoff = 0, roff = 0;
-    if (lane < count) {
-        pid = a.perm[first + lane];
+    if (g < count) {
+        pid = a.perm[first + g];
         if (pid < 0 || pid >= a.n_pairs) pid = -1;
     }
     if (pid >= 0) {
@@ -516,30 +563,34 @@ __device__ void do_inter_group(const Args& a, int first, int count, uint8_t* pro
         m = (int)(a.q_offsets[qi + 1] - qoff);
         roff = a.r_offsets[ri];
         n = (int)(a.r_offsets[ri + 1] - roff);
-        // the slot must hold one boundary cell per column of this pair
-        const int64_t need = (int64_t)((n + 7) / 8) * kWave * (WIDE ? 16 : 8);
+        // the slot must hold one boundary cell per column for every group
+        const int64_t need = (int64_t)((n + 7) / 8) * G * SW * 4;
         if (need > a.slot_words) {
-            atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
-            sw_result bad;
-            bad.score = bad.q_start = bad.q_end = bad.r_start = bad.r_end = -1;
-            a.out[pid] = bad;
+            if (u == 0) {
+                atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+                sw_result bad;
+                bad.score = bad.q_start = bad.q_end = bad.r_start = bad.r_end = -1;
+                a.out[pid] = bad;
+            }
             pid = -1;
             m = n = 0;
         }
     }
-    const Best f = inter_sweep<R, false, WIDE>(a, prof, slot, qoff, m, roff, n, 0);
+    uint8_t* prof = lds;
+    uint4* xbuf = reinterpret_cast<uint4*>(lds + kNumCodes * kWave * R);
+    const Best f = group_sweep<R, P, false, WIDE>(a, prof, xbuf, slot, qoff, m, roff, n, 0);
     const bool has = f.s > 0;
-    const Best r = inter_sweep<R, true, WIDE>(a, prof, slot, qoff + (has ? f.i : 0), has ? f.i + 1 : 0,
-                                              roff + (has ? f.j : 0), has ? f.j + 1 : 0, f.s);
-    if (pid >= 0) {
+    const Best r = group_sweep<R, P, true, WIDE>(a, prof, xbuf, slot, qoff + (has ? f.i : 0), has ? f.i + 1 : 0,
+                                                 roff + (has ? f.j : 0), has ? f.j + 1 : 0, f.s);
+    if (pid >= 0 && u == 0) {
         if (has && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
         write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
     }
 }
 
 // ------------------------------------------------------------------ kernels
-// Work items, in queue order: groups of up to 64 wide pairs, then groups of
-// up to 64 narrow pairs, each run by one wave, lane k taking pair k.
+// Work items, in queue order: single pairs over 64 lanes (longest first),
+// groups of 4 pairs over 16 lanes each, groups of 64 pairs one per lane.
 template <int R>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_persistent(Args a)
 {
@@ -547,45 +598,40 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
     // the counters come from the scan; clamp them so that a bookkeeping error
     // can never index past the permutation
-    const int n_wide = min(max(a.counters[kCntWide], 0), (int)a.n_pairs);
-    const int n_inter = min(max(a.counters[kCntInter], 0), (int)a.n_pairs - n_wide);
-    const int n_wgroups = (n_wide + kWave - 1) / kWave;
-    const int n_groups = (n_inter + kWave - 1) / kWave;
-    const int total = n_wgroups + n_groups;
+    const int n64 = min(max(a.counters[kCntP64], 0), (int)a.n_pairs);
+    const int n16 = min(max(a.counters[kCntP16], 0), (int)a.n_pairs - n64);
+    const int n1 = min(max(a.counters[kCntP1], 0), (int)a.n_pairs - n64 - n16);
+    const int i16 = (n16 + 3) / 4, i1 = (n1 + kWave - 1) / kWave;
+    const int total = n64 + i16 + i1;
+#pragma unroll 1
     for (;;) {
         int item = 0;
         if ((threadIdx.x & (kWave - 1)) == 0) item = atomicAdd(&a.counters[kCntHead], 1);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total) break;
-        if (item < n_wgroups) {
-            do_inter_group<R, true>(a, item * kWave, min(kWave, n_wide - item * kWave), lds, slot);
+        if (item < n64) {
+            do_group<R, 64, true>(a, item, 1, lds, slot);
+        } else if (item < n64 + i16) {
+            const int k = item - n64;
+            do_group<R, 16, false>(a, n64 + 4 * k, min(4, n16 - 4 * k), lds, slot);
         } else {
-            const int g = item - n_wgroups;
-            do_inter_group<R, false>(a, n_wide + g * kWave, min(kWave, n_inter - g * kWave), lds, slot);
+            const int k = item - n64 - i16;
+            do_group<R, 1, false>(a, n64 + n16 + kWave * k, min(kWave, n1 - kWave * k), lds, slot);
         }
     }
 }
 
-template <int R, bool WIDE>
+template <int R, int P, bool WIDE>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_plain(Args a, int first, int count)
 {
+    constexpr int G = kWave / P;
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t* slot = a.scratch + (int64_t)blockIdx.x * a.slot_words;
     first = max(first, 0);
     count = min(count, (int)a.n_pairs - first);
-    const int groups = (count + kWave - 1) / kWave;
-    for (int g = blockIdx.x; g < groups; g += gridDim.x)
-        do_inter_group<R, WIDE>(a, first + g * kWave, min(kWave, count - g * kWave), lds, slot);
-}
-
-// Longest sequence of a set (for sizing the scratch slots).
-__global__ void k_max_len(const int64_t* __restrict__ offs, int64_t n, int32_t* out)
-{
-    int64_t best = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-        best = max(best, offs[k + 1] - offs[k]);
-    best = min(best, (int64_t)0x7FFFFFFF);
-    if (best > 0) atomicMax(out, (int32_t)best);
+    const int items = (count + G - 1) / G;
+    for (int k = blockIdx.x; k < items; k += gridDim.x)
+        do_group<R, P, WIDE>(a, first + G * k, min(G, count - G * k), lds, slot);
 }
 
 // ASCII -> packed.  Thread t writes the 32 residues of high word t: positions
@@ -624,6 +670,15 @@ __device__ __forceinline__ int ceil_log2(int64_t x)
     int b = 0;
     while (((int64_t)1 << b) < x) ++b;
     return b;
+}
+
+// Lanes per pair of a work cell: 1 for the short-pair cells, 16 for long
+// pairs up to kMaxP16Len residues, 64 beyond.
+__device__ __forceinline__ int cell_kind(int cell)
+{
+    if (cell < kInterCells) return 1;
+    const int bucket = (cell - kInterCells) / kWideCostBins;
+    return (1 << bucket) <= kMaxP16Len ? 16 : 64;
 }
 
 // Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
@@ -694,26 +749,32 @@ __global__ void k_prepare(Args a)
 __global__ __launch_bounds__(1024) void k_scan(Args a)
 {
     __shared__ int part[1024];
-    __shared__ int nw[1024];
+    __shared__ int n64s[1024];
+    __shared__ int n16s[1024];
     const int t = threadIdx.x;
     constexpr int per = (kNumCells + 1023) / 1024;
     const int lo = t * per, hi = min(kNumCells, lo + per);
-    int sum = 0, waves = 0;
+    int sum = 0, c64 = 0, c16 = 0;
     for (int rk = lo; rk < hi; ++rk) {
         const int cell = a.rank_cell[rk];
         const int c = a.cell_count[cell];
         sum += c;
-        if (cell >= kInterCells) waves += c;
+        const int kind = cell_kind(cell);
+        if (kind == 64) c64 += c;
+        else if (kind == 16) c16 += c;
     }
     part[t] = sum;
-    nw[t] = waves;
+    n64s[t] = c64;
+    n16s[t] = c16;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
         const int v = t >= o ? part[t - o] : 0;
-        const int w = t >= o ? nw[t - o] : 0;
+        const int w = t >= o ? n64s[t - o] : 0;
+        const int x = t >= o ? n16s[t - o] : 0;
         __syncthreads();
         part[t] += v;
-        nw[t] += w;
+        n64s[t] += w;
+        n16s[t] += x;
         __syncthreads();
     }
     int run = part[t] - sum;  // exclusive prefix
@@ -726,8 +787,9 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
     }
     if (t == 1023) {
         a.rank_start[kNumCells] = part[1023];
-        a.counters[kCntWide] = nw[1023];
-        a.counters[kCntInter] = part[1023] - nw[1023];
+        a.counters[kCntP64] = n64s[1023];
+        a.counters[kCntP16] = n16s[1023];
+        a.counters[kCntP1] = part[1023] - n64s[1023] - n16s[1023];
     }
 }
 
@@ -741,13 +803,17 @@ __global__ void k_scatter(Args a)
 }
 
 // ------------------------------------------------------------------ launchers
-size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * R; }
+size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * R + kXbufBytes; }
 
-int64_t slot_words(int inter_max_len, int max_ref_len)
+int64_t slot_words()
 {
-    const int64_t narrow = (int64_t)((inter_max_len + 7) / 8) * kWave * 8;
-    const int64_t wide = (int64_t)((std::min(max_ref_len, SW_MAX_SEQ_LEN) + 7) / 8) * kWave * 16;
-    return std::max<int64_t>(narrow, wide);
+    // [chunk][group][8 cells]: 64 groups of one lane over at most 128 chunks
+    // (narrow), 4 groups over 512 chunks (16 lanes, narrow), 1 group over
+    // 8192 chunks (64 lanes, wide, two words per cell)
+    const int64_t p1 = (int64_t)kMaxInterChunks * 64 * 8;
+    const int64_t p16 = (int64_t)(kMaxP16Len / 8) * 4 * 8;
+    const int64_t p64 = (int64_t)((SW_MAX_SEQ_LEN + 7) / 8) * 1 * 16;
+    return std::max(p1, std::max(p16, p64));
 }
 
 __global__ void k_pack_header(PackedHeader* h, int64_t n)
@@ -801,41 +867,43 @@ hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream)
 }
 
 template <int R>
-static hipError_t launch_plain_r(const Args& a, bool wide, int first, int count, int grid, hipStream_t stream)
+static hipError_t launch_plain_r(const Args& a, int kind, int first, int count, int grid, hipStream_t stream)
 {
-    if (wide)
-        hipLaunchKernelGGL((k_plain<R, true>), dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
+    const size_t lds = lds_bytes(R);
+    if (kind == 64)
+        hipLaunchKernelGGL((k_plain<R, 64, true>), dim3(grid), dim3(kWave), lds, stream, a, first, count);
+    else if (kind == 16)
+        hipLaunchKernelGGL((k_plain<R, 16, false>), dim3(grid), dim3(kWave), lds, stream, a, first, count);
     else
-        hipLaunchKernelGGL((k_plain<R, false>), dim3(grid), dim3(kWave), lds_bytes(R), stream, a, first, count);
+        hipLaunchKernelGGL((k_plain<R, 1, false>), dim3(grid), dim3(kWave), lds, stream, a, first, count);
     return hipGetLastError();
 }
 
-hipError_t launch_plain(const Args& a, bool wide, int first, int count, int grid, hipStream_t stream)
+hipError_t launch_plain(const Args& a, int kind, int first, int count, int grid, hipStream_t stream)
 {
     switch (a.rows_per_lane) {
-    case 16: return launch_plain_r<16>(a, wide, first, count, grid, stream);
-    case 32: return launch_plain_r<32>(a, wide, first, count, grid, stream);
+    case 16: return launch_plain_r<16>(a, kind, first, count, grid, stream);
+    case 32: return launch_plain_r<32>(a, kind, first, count, grid, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_max_len(const int64_t* offs, int64_t n, int32_t* out, hipStream_t stream)
+template <int R>
+static hipError_t set_attrs_r()
 {
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, out, 1, 0);
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
-    hipLaunchKernelGGL(k_max_len, dim3((unsigned)blocks), dim3(256), 0, stream, offs, n, out);
-    return hipGetLastError();
+    const int bytes = (int)lds_bytes(R);
+    const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+    hipError_t e = hipFuncSetAttribute((const void*)k_persistent<R>, at, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_plain<R, 1, false>, at, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_plain<R, 16, false>, at, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_plain<R, 64, true>, at, bytes);
+    return e;
 }
 
 hipError_t set_kernel_attributes()
 {
-    const int bytes32 = (int)lds_bytes(32);
-    hipError_t e = hipFuncSetAttribute((const void*)k_persistent<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       bytes32);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_plain<32, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_plain<32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes32);
+    hipError_t e = set_attrs_r<16>();
+    return e == hipSuccess ? set_attrs_r<32>() : e;
 }
 
 }  // namespace swk

@@ -44,6 +44,8 @@ constexpr int kWave = 64;
 constexpr int kMaxInterStrips = 64;    // ceil(inter_max_len / rows_per_lane) <= this
 constexpr int kMaxInterChunks = 128;   // ceil(inter_max_len / 8) <= this
 constexpr int kMaxInterLen = 1024;
+constexpr int kMaxP16Len = 4096;      // longer pairs get a whole wave
+constexpr int kXbufBytes = 64 * 64;   // LDS exchange buffer: 16 words per lane
 constexpr int kWideCostBins = 512;     // floor(16 * log2(m*n)) for long (wide) pairs
 constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
 constexpr int kInterCells = kMaxInterStrips * kMaxInterChunks;
@@ -53,9 +55,9 @@ constexpr int kNumCells = kInterCells + kWideCells;
 // counters[] slots in the workspace
 enum {
     kCntHead = 0,   // persistent work-queue head
-    kCntWide = 1,   // number of long pairs (wide lane-per-pair variant)
-    kCntInter = 2,  // number of short pairs (narrow variant)
-    kCntMaxLen = 3, // longest reference sequence of the call
+    kCntP64 = 1,    // pairs aligned by 64 lanes (longest)
+    kCntP16 = 2,    // pairs aligned by 16 lanes
+    kCntP1 = 3,     // pairs aligned by one lane
     kNumCounters = 16
 };
 enum { kErrRange = 1, kErrCode = 2, kErrInternal = 4 };
@@ -90,11 +92,10 @@ struct Args {
 hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err, hipStream_t stream);
 hipError_t launch_prepare(const Args& a, hipStream_t stream);  // zero, classify, scan, scatter
 hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream);
-hipError_t launch_plain(const Args& a, bool wide, int first, int count, int grid, hipStream_t stream);
-hipError_t launch_max_len(const int64_t* offs, int64_t n, int32_t* out, hipStream_t stream);
+hipError_t launch_plain(const Args& a, int kind, int first, int count, int grid, hipStream_t stream);
 hipError_t set_kernel_attributes();
 size_t lds_bytes(int rows_per_lane);
-int64_t slot_words(int inter_max_len, int max_ref_len);
+int64_t slot_words();
 void matrix_ncbi(int8_t out[kNumSym * kNumSym], char letters[kNumSym + 1]);
 const char* code_order();
 
