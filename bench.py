@@ -42,6 +42,10 @@ def main():
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--inter-max", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="persistent form launched directly instead of replayed as a HIP graph")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -55,6 +59,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        calibrate_copy(torch, dev, args.calibrate_copy)
+        return
     sw.lib()
     if args.rows_per_lane or args.inter_max or args.blocks_per_cu:
         sw.set_tuning(args.rows_per_lane, args.inter_max, args.blocks_per_cu)
@@ -95,6 +102,7 @@ def main():
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
                torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        sw.timing_read(stream)  # forget earlier timed calls
         torch.cuda.synchronize()
         t = time.perf_counter()
         for e0, e1, e2 in ev:
@@ -105,21 +113,25 @@ def main():
             rc = L.sw_batch_align(ctypes.c_void_p(packed_d.data_ptr()), ctypes.c_void_p(offs_d.data_ptr()),
                                   ps.n_seqs, ctypes.c_void_p(pairs_d.data_ptr()), ps.n_pairs,
                                   ctypes.byref(sc), ctypes.c_void_p(out_d.data_ptr()), ctypes.c_void_p(sptr),
-                                  flags)
+                                  flags | sw.TIMED)
             if rc:
                 raise sw.SwError(rc, "sw_batch_align")
             e2.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
+        kernel_ms, calls = sw.timing_read(stream)
+        assert calls == steps, (calls, steps)
+        kernel_ms /= steps
         align_ms = [e1.elapsed_time(e2) for _, e1, e2 in ev]
         pack_ms = [e0.elapsed_time(e1) for e0, e1, _ in ev]
-        log("%s: %d steps, wall %.3fs, align %.2f ms (min %.2f), pack %.3f ms" % (
-            label, steps, wall, np.mean(align_ms), np.min(align_ms), np.mean(pack_ms)))
-        return wall, float(np.mean(align_ms)), float(np.mean(pack_ms))
+        log("%s: %d steps, wall %.3fs, align %.2f ms (min %.2f), kernel %.2f ms, pack %.3f ms" % (
+            label, steps, wall, np.mean(align_ms), np.min(align_ms), kernel_ms, np.mean(pack_ms)))
+        return wall, float(np.mean(align_ms)), float(np.mean(pack_ms)), kernel_ms
 
     # headline: persistent + graph
     log("warmup + timed persistent form")
-    wall, align_ms, pack_ms = timed(sw.PERSISTENT, args.steps, args.warmup, "persistent")
+    pflags = sw.NO_GRAPH if args.no_graph else sw.PERSISTENT
+    wall, align_ms, pack_ms, kernel_ms = timed(pflags, args.steps, args.warmup, "persistent")
     ms_per_step = wall / args.steps * 1e3
     gcups = cells * args.steps / wall / 1e9
     aps = ps.n_pairs * args.steps / wall
@@ -135,10 +147,18 @@ def main():
     log("sampled parity %d/%d" % (n_ok, len(sample)))
 
     plain_steps = args.plain_steps if args.plain_steps is not None else max(1, args.steps // 2)
-    pwall, palign_ms, _ = timed(sw.PLAIN, plain_steps, 1, "plain")
-    pgcups = cells * plain_steps / pwall / 1e9
+    plain = None
+    if plain_steps > 0:
+        pwall, palign_ms, _, pkernel_ms = timed(sw.PLAIN, plain_steps, 1, "plain")
+        pgcups = cells * plain_steps / pwall / 1e9
+        plain = {"gcups": round(pgcups, 2), "alignments_per_s": round(ps.n_pairs * plain_steps / pwall, 1),
+                 "ms_per_step": round(pwall / plain_steps * 1e3, 3), "align_ms": round(palign_ms, 3),
+                 "kernel_ms": round(pkernel_ms, 3), "steps": plain_steps}
 
-    achieved = ALGO_OPS_PER_CELL * cells / (align_ms * 1e-3) / 1e12
+    # dominant kernel: the persistent alignment kernel, timed by HIP events
+    # recorded by the library on the launch stream around that launch alone
+    achieved = ALGO_OPS_PER_CELL * cells / (kernel_ms * 1e-3) / 1e12
+    R = tuning["rows_per_lane"]
     res = {
         "metric": "GCUPS (cell updates/s, full m*n matrix per pair incl. start-coordinate pass), persistent batched form",
         "value": round(gcups, 2),
@@ -159,20 +179,57 @@ def main():
         "alignments_per_s": round(aps, 1),
         "align_ms": round(align_ms, 3),
         "pack_ms": round(pack_ms, 3),
-        "plain": {"gcups": round(pgcups, 2), "alignments_per_s": round(ps.n_pairs * plain_steps / pwall, 1),
-                  "ms_per_step": round(pwall / plain_steps * 1e3, 3), "align_ms": round(palign_ms, 3),
-                  "steps": plain_steps},
-        "persistent_over_plain": round(gcups / pgcups, 3),
+        "kernel_ms": round(kernel_ms, 3),
+        "plain": plain,
+        "persistent_over_plain": round(gcups / plain["gcups"], 3) if plain else None,
         "parity_sample": "%d/%d bit-exact vs CPU oracle" % (n_ok, len(sample)),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
-                     "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
-                     "kernel": "persistent align (prepare + k_persistent graph), 8 int32 ops per cell"},
+                     "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
+                     "traffic": stored_traffic(R, ps.n_pairs),
+                     "kernel": "k_persistent<%d>, %d int32 ops per cell x %d cells per launch" % (
+                         R, ALGO_OPS_PER_CELL, cells)},
         "paper_context": "paper: 690.6 M alignments/s and 176.3 TCUPS peak on 20,184 V100 GPUs "
                          "(whole application, multi-node; not a 1-GPU target)",
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def calibrate_copy(torch, dev, nbytes):
+    """A plain device-to-device copy of a known size, for scaling the HBM
+    byte counters (FETCH_SIZE, WRITE_SIZE) of the profiler."""
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copied %d bytes 3 times" % (src.numel() * 4))
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_1m-lognormal280_traffic.md")
+
+
+def stored_traffic(R, n_pairs):
+    """HBM bytes per launch of the persistent kernel as measured by the
+    counter runs recorded in the profiles folder, or None when the kernel
+    source or the kernel shape changed since they were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
+    fields = {k[2:].strip(): v.strip().strip("`") for k, v in fields.items()}
+    src = os.path.join(ROOT, "paper_2303_01845_amd", "csrc", "sw_device.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if (fields.get("kernel source sha256") != digest or fields.get("rows per lane") != str(R)
+            or fields.get("pairs") != str(n_pairs)):
+        return None
+    try:
+        return int(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(ps, seconds):

@@ -76,6 +76,7 @@ typedef struct {
 #define SW_PLAIN 1u      /* one launch per length bucket, static work split, no queue, no graph */
 #define SW_VALIDATE 2u   /* synchronise before returning and report SW_ERANGE / SW_ECODE found on the device */
 #define SW_NO_GRAPH 4u   /* persistent form without HIP-graph capture */
+#define SW_TIMED 8u      /* bracket the alignment kernels of this call with HIP events (see sw_timing_read) */
 
 /*
  * Bytes a packed buffer needs for n_residues residues (header, two residue
@@ -106,7 +107,8 @@ SW_API int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, 
  *   pairs_dev     int32[2 * n_pairs]: (query index, reference index) per pair
  *   scoring       host struct (see above)
  *   out_dev       sw_result[n_pairs], written in pair order
- *   flags         SW_PERSISTENT (0) | SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH
+ *   flags         SW_PERSISTENT (0) | SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH |
+ *                 SW_TIMED
  * A pair with an index outside [0, n_seqs) or a sequence longer than
  * SW_MAX_SEQ_LEN gets score -1 and coordinates -1 and raises SW_ERANGE on the
  * next check; an empty sequence gives score 0.  n_pairs == 0 does nothing.
@@ -139,10 +141,24 @@ SW_API int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev,
 SW_API int sw_check(void* stream);
 
 /*
+ * Device time of the alignment kernels of the calls made with SW_TIMED on
+ * `stream` since the previous read: the persistent kernel of each persistent
+ * call (the sorting kernels before it are not included; with graph replay the
+ * two parts are separate graphs with the events between them), or the
+ * per-bucket launch series of each SW_PLAIN call.  Synchronises `stream`,
+ * writes the summed milliseconds to *kernel_ms and the number of calls to
+ * *calls, and forgets them.  At most 4096 timed calls may be outstanding on a
+ * stream; a further SW_TIMED call returns SW_ENOMEM before launching anything.
+ * Errors: SW_EINVAL (null output pointer), SW_EDEVICE.
+ */
+SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
+
+/*
  * Kernel shape used by later calls on the current device.  rows_per_lane is
  * the number of query rows each lane keeps in registers (16 or 32);
  * inter_max_len is the longest pair (max of both lengths, 64..1024) that is
- * aligned one pair per lane, longer pairs get one 64-lane wave each;
+ * aligned one pair per lane, longer pairs are spread over a group of 16 lanes
+ * (up to 4096 residues) or a whole 64-lane wave;
  * blocks_per_cu sets the persistent grid (1..8).  Any field <= 0 keeps the
  * current value.  Results never depend on these values.
  */
@@ -157,7 +173,7 @@ SW_API int sw_get_tuning(sw_tuning* t);
 /*
  * Autotuner: time sw_batch_align (persistent form) on this workload for every
  * candidate kernel shape (rows_per_lane 16/32, inter_max_len 256/512/1024 --
- * the length above which a pair gets a whole wave instead of one lane --
+ * the length above which a pair gets a lane group instead of one lane --
  * and blocks_per_cu occupancy-derived or 2), `reps` timed runs each, require
  * every shape to give byte-identical results, keep the fastest as the current
  * tuning and report it in *chosen (and its time per call in *best_ms, may be

@@ -29,9 +29,11 @@ PERSISTENT = 0
 PLAIN = 1
 VALIDATE = 2
 NO_GRAPH = 4
+TIMED = 8
 
 # every function the C header declares
-EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_check", "sw_set_tuning",
+EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_check", "sw_timing_read",
+           "sw_set_tuning",
            "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
            "sw_server_submit", "sw_server_poll", "sw_server_wait", "sw_server_stats",
            "sw_server_request_bytes", "sw_server_destroy")
@@ -80,6 +82,8 @@ def lib():
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
         L.sw_check.argtypes = [ctypes.c_void_p]
+        L.sw_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
         L.sw_server_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.POINTER(Scoring), ctypes.c_size_t, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_void_p)]
@@ -181,6 +185,14 @@ def align_sets(q_packed, q_offsets, r_packed, r_offsets, pairs, gap_open: int = 
 def check(stream=None):
     """Synchronise and raise for device-detected errors (SW_ERANGE / SW_ECODE)."""
     _check(lib().sw_check(_stream_ptr(stream)), "sw_check")
+
+
+def timing_read(stream=None):
+    """(kernel milliseconds, calls) summed over the SW_TIMED calls on `stream`
+    since the previous read; synchronises the stream."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().sw_timing_read(_stream_ptr(stream), ctypes.byref(ms), ctypes.byref(n)), "sw_timing_read")
+    return ms.value, n.value
 
 
 def set_tuning(rows_per_lane: int = 0, inter_max_len: int = 0, blocks_per_cu: int = 0):

@@ -148,11 +148,32 @@ struct Workspace {
     int64_t scratch_words = 0;
     uint32_t* scratch = nullptr;
     int32_t* host_rank_start = nullptr;  // pinned, plain form only
-    std::map<GraphKey, hipGraphExec_t> graphs;
+    // persistent form: the sorting kernels and the persistent kernel are two
+    // graphs so that timing events can sit between them
+    struct Graphs {
+        hipGraphExec_t prepare = nullptr, align = nullptr;
+    };
+    std::map<GraphKey, Graphs> graphs;
+    // SW_TIMED: event pairs recorded and not yet read, and a pool to reuse
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, event_pool;
+
+    void drop_graphs()
+    {
+        for (auto& g : graphs) {
+            (void)hipGraphExecDestroy(g.second.prepare);
+            (void)hipGraphExecDestroy(g.second.align);
+        }
+        graphs.clear();
+    }
 
     ~Workspace()
     {
-        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        drop_graphs();
+        for (auto& e : timed) event_pool.push_back(e);
+        for (auto& e : event_pool) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
         (void)hipFree(pair_cell);
         (void)hipFree(perm);
         (void)hipFree(cell_count);
@@ -190,9 +211,9 @@ int upload_ordering(Device& d)
     HIP_TRY(hipMemcpy(d.rank_cell_plain, d.ord.rank_cell_plain.data(), sizeof(int32_t) * kNumCells,
                       hipMemcpyHostToDevice),
             "upload ordering");
-    for (auto& w : d.ws) {  // graphs captured the old tables' contents by pointer only; still valid
-        (void)w;
-    }
+    // Graphs read the tables through the same device pointers, so captured
+    // graphs stay valid; the callers drop them anyway because the kernel
+    // shape changed.
     return SW_OK;
 }
 
@@ -262,10 +283,7 @@ int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, Workspace** ou
         w.pair_cap = cap;
         changed = true;
     }
-    if (changed) {
-        for (auto& g : w.graphs) (void)hipGraphExecDestroy(g.second);
-        w.graphs.clear();
-    }
+    if (changed) w.drop_graphs();
     *out = &w;
     return SW_OK;
 }
@@ -280,8 +298,47 @@ int ensure_scratch(Workspace& w, int64_t need)
         return rc;
     }
     w.scratch_words = need;
-    for (auto& g : w.graphs) (void)hipGraphExecDestroy(g.second);
-    w.graphs.clear();
+    w.drop_graphs();
+    return SW_OK;
+}
+
+// Capture what `launch` enqueues on the device's capture stream as a graph.
+template <typename F>
+int capture(Device& d, F launch, hipGraphExec_t* out)
+{
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(d.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e1 = launch(d.capture_stream);
+    hipError_t e2 = hipStreamEndCapture(d.capture_stream, &g);
+    if (e1 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return dev_error(e1, "capture launch");
+    }
+    HIP_TRY(e2, "end capture");
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(e3, "graph instantiate");
+    *out = ex;
+    return SW_OK;
+}
+
+constexpr size_t kMaxTimed = 4096;
+
+// Event pair for one SW_TIMED call (from the pool, else new).
+int timing_events(Workspace& w, std::pair<hipEvent_t, hipEvent_t>* ev)
+{
+    if (!w.event_pool.empty()) {
+        *ev = w.event_pool.back();
+        w.event_pool.pop_back();
+        return SW_OK;
+    }
+    HIP_TRY(hipEventCreate(&ev->first), "hipEventCreate");
+    hipError_t e = hipEventCreate(&ev->second);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev->first);
+        return dev_error(e, "hipEventCreate");
+    }
     return SW_OK;
 }
 
@@ -327,7 +384,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
                   const sw_scoring* scoring, sw_result* out_dev, void* stream_, uint32_t flags)
 {
     if (!scoring || n_pairs < 0 || n_q < 0 || n_r < 0) return SW_EINVAL;
-    if (flags & ~(SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH)) return SW_EINVAL;
+    if (flags & ~(SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH | SW_TIMED)) return SW_EINVAL;
     if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
         scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
         return SW_EINVAL;
@@ -376,6 +433,26 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     a.rows_per_lane = d.R;
     a.inter_max_len = d.inter_max;
 
+    const bool timed = flags & SW_TIMED;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (timed) {
+        if (w.timed.size() >= kMaxTimed) return SW_ENOMEM;
+        if ((rc = timing_events(w, &ev))) return rc;
+        w.event_pool.push_back(ev);  // back in the pool until recorded
+    }
+    auto begin_timed = [&]() -> hipError_t {
+        return timed ? hipEventRecord(ev.first, stream) : hipSuccess;
+    };
+    auto end_timed = [&]() -> hipError_t {
+        if (!timed) return hipSuccess;
+        hipError_t e = hipEventRecord(ev.second, stream);
+        if (e == hipSuccess) {
+            w.event_pool.pop_back();
+            w.timed.push_back(ev);
+        }
+        return e;
+    };
+
     if (flags & SW_PLAIN) {
         a.rank_cell = d.rank_cell_plain;
         HIP_TRY(launch_prepare(a, stream), "prepare launch");
@@ -383,6 +460,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
                                hipMemcpyDeviceToHost, stream),
                 "bucket sizes");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        HIP_TRY(begin_timed(), "hipEventRecord");
         for (const auto& b : d.ord.buckets) {
             const int first = w.host_rank_start[b.rank_begin];
             const int count = w.host_rank_start[b.rank_end] - first;
@@ -391,37 +469,38 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             const int items = (count + per_item - 1) / per_item;
             HIP_TRY(launch_plain(a, b.kind, first, count, std::min(items, grid), stream), "plain launch");
         }
+        HIP_TRY(end_timed(), "hipEventRecord");
     } else {
         a.rank_cell = d.rank_cell_persistent;
         if (flags & SW_NO_GRAPH) {
             HIP_TRY(launch_prepare(a, stream), "prepare launch");
+            HIP_TRY(begin_timed(), "hipEventRecord");
             HIP_TRY(launch_persistent(a, grid, stream), "persistent launch");
+            HIP_TRY(end_timed(), "hipEventRecord");
         } else {
             GraphKey key{q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev,
                          n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, grid, sw_words};
             auto it = w.graphs.find(key);
             if (it == w.graphs.end()) {
                 if (w.graphs.size() >= 16) {
-                    (void)hipGraphExecDestroy(w.graphs.begin()->second);
+                    (void)hipGraphExecDestroy(w.graphs.begin()->second.prepare);
+                    (void)hipGraphExecDestroy(w.graphs.begin()->second.align);
                     w.graphs.erase(w.graphs.begin());
                 }
-                hipGraph_t g = nullptr;
-                HIP_TRY(hipStreamBeginCapture(d.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-                hipError_t e1 = launch_prepare(a, d.capture_stream);
-                hipError_t e2 = e1 == hipSuccess ? launch_persistent(a, grid, d.capture_stream) : e1;
-                hipError_t e3 = hipStreamEndCapture(d.capture_stream, &g);
-                if (e2 != hipSuccess) {
-                    if (g) (void)hipGraphDestroy(g);
-                    return dev_error(e2, "capture launch");
+                Workspace::Graphs gs;
+                rc = capture(d, [&](hipStream_t s) { return launch_prepare(a, s); }, &gs.prepare);
+                if (rc) return rc;
+                rc = capture(d, [&](hipStream_t s) { return launch_persistent(a, grid, s); }, &gs.align);
+                if (rc) {
+                    (void)hipGraphExecDestroy(gs.prepare);
+                    return rc;
                 }
-                HIP_TRY(e3, "end capture");
-                hipGraphExec_t ex = nullptr;
-                hipError_t e4 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                HIP_TRY(e4, "graph instantiate");
-                it = w.graphs.emplace(key, ex).first;
+                it = w.graphs.emplace(key, gs).first;
             }
-            HIP_TRY(hipGraphLaunch(it->second, stream), "graph launch");
+            HIP_TRY(hipGraphLaunch(it->second.prepare, stream), "graph launch");
+            HIP_TRY(begin_timed(), "hipEventRecord");
+            HIP_TRY(hipGraphLaunch(it->second.align, stream), "graph launch");
+            HIP_TRY(end_timed(), "hipEventRecord");
         }
     }
     if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
@@ -442,6 +521,33 @@ int sw_check(void* stream)
     int rc = get_device(&d);
     if (rc) return rc;
     return read_and_clear_errors(*d, (hipStream_t)stream);
+}
+
+int sw_timing_read(void* stream_, double* kernel_ms, int64_t* calls)
+{
+    if (!kernel_ms || !calls) return SW_EINVAL;
+    hipStream_t stream = (hipStream_t)stream_;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* d = nullptr;
+    int rc = get_device(&d);
+    if (rc) return rc;
+    *kernel_ms = 0.0;
+    *calls = 0;
+    auto it = d->ws.find(stream);
+    if (it == d->ws.end()) return SW_OK;
+    Workspace& w = *it->second;
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    double total = 0.0;
+    for (auto& e : w.timed) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+        total += ms;
+    }
+    *kernel_ms = total;
+    *calls = (int64_t)w.timed.size();
+    for (auto& e : w.timed) w.event_pool.push_back(e);
+    w.timed.clear();
+    return SW_OK;
 }
 
 int sw_set_tuning(const sw_tuning* t)
@@ -466,10 +572,7 @@ int sw_set_tuning(const sw_tuning* t)
         rc = upload_ordering(*d);
         if (rc) return rc;
     }
-    for (auto& w : d->ws) {  // graphs bake in the kernel shape
-        for (auto& g : w.second->graphs) (void)hipGraphExecDestroy(g.second);
-        w.second->graphs.clear();
-    }
+    for (auto& w : d->ws) w.second->drop_graphs();  // graphs bake in the kernel shape
     return SW_OK;
 }
 

@@ -231,3 +231,20 @@ def test_two_sets_match_one_set(sw):
     got = sw.align_sets(qb.packed, qb.offsets, rb.packed, rb.offsets, torch.from_numpy(pairs).cuda()).cpu().numpy()
     one = P.PairSet(ps.ascii, ps.offsets, np.stack([q_idx[pairs[:, 0]], r_idx[pairs[:, 1]]], 1).astype(np.int32))
     assert_same(got, expect(one), one, "two sets")
+
+
+def test_timed_calls(sw):
+    """SW_TIMED changes no result; the timing read counts every timed call of
+    each form once and then forgets them."""
+    import torch
+    ps = P.config_small(300)
+    exp = expect(ps)
+    stream = torch.cuda.current_stream()
+    sw.timing_read(stream)
+    for flags, label in [(0, "persistent+graph"), (sw.NO_GRAPH, "persistent"), (sw.PLAIN, "plain")]:
+        say("timed, %s" % label)
+        for _ in range(2):
+            assert_same(gpu_align(sw, ps, flags=flags | sw.TIMED), exp, ps, "timed " + label)
+        ms, calls = sw.timing_read(stream)
+        assert calls == 2 and ms > 0.0, (label, ms, calls)
+        assert sw.timing_read(stream) == (0.0, 0)
