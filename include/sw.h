@@ -155,8 +155,9 @@ SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
 
 /*
  * Kernel shape used by later calls on the current device.  rows_per_lane is
- * the number of query rows each lane keeps in registers (16 or 32);
- * inter_max_len is the longest pair (max of both lengths, 64..1024) that is
+ * the number of query rows each lane keeps in registers (8 or 16);
+ * inter_max_len is the longest pair (max of both lengths, 64..1024, at most
+ * 64 rows_per_lane) that is
  * aligned one pair per lane, longer pairs are spread over a group of 16 lanes
  * (up to 4096 residues) or a whole 64-lane wave;
  * blocks_per_cu sets the persistent grid (1..8).  Any field <= 0 keeps the
@@ -172,7 +173,7 @@ SW_API int sw_get_tuning(sw_tuning* t);
 
 /*
  * Autotuner: time sw_batch_align (persistent form) on this workload for every
- * candidate kernel shape (rows_per_lane 16/32, inter_max_len 256/512/1024 --
+ * candidate kernel shape (rows_per_lane 16/8, inter_max_len 256/512/1024 --
  * the length above which a pair gets a lane group instead of one lane --
  * and blocks_per_cu occupancy-derived or 2), `reps` timed runs each, require
  * every shape to give byte-identical results, keep the fastest as the current

@@ -553,8 +553,11 @@ int sw_timing_read(void* stream_, double* kernel_ms, int64_t* calls)
 int sw_set_tuning(const sw_tuning* t)
 {
     if (!t) return SW_EINVAL;
-    if (t->rows_per_lane > 0 && t->rows_per_lane != 16 && t->rows_per_lane != 32) return SW_EINVAL;
+    if (t->rows_per_lane > 0 && t->rows_per_lane != 8 && t->rows_per_lane != 16) return SW_EINVAL;
     if (t->inter_max_len > 0 && (t->inter_max_len < 64 || t->inter_max_len > kMaxInterLen)) return SW_EINVAL;
+    if (t->rows_per_lane > 0 && t->inter_max_len > 0 &&
+        (t->inter_max_len + t->rows_per_lane - 1) / t->rows_per_lane > kMaxInterStrips)
+        return SW_EINVAL;
     if (t->blocks_per_cu > 8) return SW_EINVAL;
     std::lock_guard<std::mutex> lock(g_mutex);
     Device* d = nullptr;
@@ -610,7 +613,7 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
         int R, im, bpc;
     };
     std::vector<Cand> cands;
-    for (int R : {16, 32})
+    for (int R : {16, 8})
         for (int im : {256, 512, 1024})
             for (int bpc : {0, 2})
                 if ((im + R - 1) / R <= kMaxInterStrips) cands.push_back({R, im, bpc});

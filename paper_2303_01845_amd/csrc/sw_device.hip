@@ -183,9 +183,23 @@ __device__ __forceinline__ void row_codes(const SeqView& qv, int row0, int M, ui
 
 // ------------------------------------------------------------------ query profile in LDS
 // Layout [code][lane][R bytes]: lane l's scores for its R rows against a
-// reference residue `code` are 16 or 32 contiguous bytes; a wave's reads of
-// one row of the layout are contiguous in lane order, so ds_read_b128 is
-// conflict-free whatever codes the lanes hold.
+// reference residue `code` are 8 or 16 contiguous bytes; a wave's reads of
+// one row of the layout are contiguous in lane order, so the 8- or 16-byte
+// reads are conflict-free whatever codes the lanes hold.
+
+// One profile entry (R bytes) as 16-byte stores, or one 8-byte store for R = 8.
+template <int R>
+__device__ __forceinline__ void store_entry(uint8_t* dst, const uint32_t (&v)[R / 4])
+{
+    if constexpr (R == 8) {
+        *reinterpret_cast<uint2*>(dst) = make_uint2(v[0], v[1]);
+    } else {
+        uint4* d4 = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+        for (int w = 0; w < R / 16; ++w) d4[w] = make_uint4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+    }
+}
+
 template <int R>
 __device__ __forceinline__ void build_profile(uint8_t* prof, int lane, const uint32_t (&qc)[R])
 {
@@ -215,18 +229,23 @@ __device__ __forceinline__ void build_profile(uint8_t* prof, int lane, const uin
         for (int w = 0; w < R / 4; ++w)
             v[w] = __builtin_amdgcn_perm(t1, t0, sel[w][0]) | __builtin_amdgcn_perm(t3, t2, sel[w][1]) |
                    __builtin_amdgcn_perm(t5, t4, sel[w][2]);
-        uint4* dst = reinterpret_cast<uint4*>(base + c * (kWave * R));
-#pragma unroll
-        for (int w = 0; w < R / 16; ++w) dst[w] = make_uint4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+        store_entry<R>(base + c * (kWave * R), v);
     }
-    uint4* dst = reinterpret_cast<uint4*>(base + kPadCode * (kWave * R));
+    uint32_t pad[R / 4];
 #pragma unroll
-    for (int w = 0; w < R / 16; ++w) dst[w] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+    for (int w = 0; w < R / 4; ++w) pad[w] = 0x80808080u;
+    store_entry<R>(base + kPadCode * (kWave * R), pad);
 }
 
 template <int R>
 __device__ __forceinline__ void load_profile(const uint8_t* prof_lane, uint32_t code, uint32_t (&w)[R / 4])
 {
+    if constexpr (R == 8) {
+        const uint2 v = *reinterpret_cast<const uint2*>(prof_lane + code * (uint32_t)(kWave * R));
+        w[0] = v.x;
+        w[1] = v.y;
+        return;
+    }
     const uint4* p = reinterpret_cast<const uint4*>(prof_lane + code * (uint32_t)(kWave * R));
 #pragma unroll
     for (int k = 0; k < R / 16; ++k) {
@@ -243,21 +262,14 @@ __device__ __forceinline__ void load_profile(const uint8_t* prof_lane, uint32_t 
 template <int SEL>
 __device__ __forceinline__ int add_sbyte(int h, uint32_t w)
 {
-    int d;
-    if constexpr (SEL == 0)
-        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
-            : "=v"(d) : "v"(h), "v"(w));
-    else if constexpr (SEL == 1)
-        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
-            : "=v"(d) : "v"(h), "v"(w));
-    else if constexpr (SEL == 2)
-        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
-            : "=v"(d) : "v"(h), "v"(w));
-    else
-        asm("v_add_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
-            : "=v"(d) : "v"(h), "v"(w));
-    return d;
+    return h + (int)(int8_t)(uint8_t)(w >> (8 * SEL));
 }
+
+// Hides what the compiler knows about the value's range (no instruction).
+// E and F are never negative; once the compiler proves that, it splits
+// max(max(d, E), F) into a signed and an unsigned max instead of one
+// v_max3_i32.
+__device__ __forceinline__ void opaque(int& v) { asm("" : "+v"(v)); }
 
 template <int R, int I>
 struct RowUnroll {
@@ -273,6 +285,8 @@ struct RowUnroll {
         const int hg = (int)__builtin_elementwise_sub_sat((uint32_t)h, go);
         E[I] = max(E[I] - ge, hg);
         F = max(F - ge, hg);
+        opaque(E[I]);
+        opaque(F);
         K[I] = max(K[I], ((uint32_t)h << TB) | tag);
         d = dn;
         if constexpr (I + 1 < R) RowUnroll<R, I + 1>::template run<TB>(H, E, K, w, d, F, tag, go, ge);
@@ -418,24 +432,33 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
             return (c < 0 || 8 * c >= N) ? 0 : (REV ? -8 * c - 7 : 8 * c);
         };
         const int T = wc + P - 1;
+        // Software pipeline: the global loads of chunk c+1 (reference window,
+        // and for lane 0 the boundary row from the slot) are issued at the
+        // start of chunk c, and the profile words of column k+1 are read from
+        // LDS before column k is computed, so neither latency sits in front of
+        // the cell updates.  Idle steps (before the first or past the last
+        // chunk) still load, so their indexes are kept inside the pair.
+        uint4 tc_n[SW];
+        uint32_t nw_n, hw_n;
+        auto fetch = [&](int cn) {
+            if (u == 0) {
+                const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
+#pragma unroll
+                for (int w = 0; w < SW; ++w)
+                    tc_n[w] = read_top ? slot4[cc * G * SW + w] : make_uint4(0, 0, 0, 0);
+            }
+            window8(rv, chunk_x(cn), nw_n, hw_n);
+        };
+        fetch(-u);
 #pragma unroll 1
         for (int t = 0; t < T; ++t) {
             const int c = t - u;
             const bool act = gact && c >= 0 && c < my_chunks;
             uint4 tc[SW];
-            if (u == 0) {
-                // idle steps (before the first or past the last chunk) still
-                // read, so keep the index inside this pair's chunks
-                const int cc = min(max(c, 0), max(my_chunks - 1, 0));
 #pragma unroll
-                for (int w = 0; w < SW; ++w)
-                    tc[w] = read_top ? slot4[cc * G * SW + w] : make_uint4(0, 0, 0, 0);
-            } else {
-#pragma unroll
-                for (int w = 0; w < SW; ++w) tc[w] = x_up[w];
-            }
-            uint32_t nw, hw;
-            window8(rv, chunk_x(c), nw, hw);
+            for (int w = 0; w < SW; ++w) tc[w] = u == 0 ? tc_n[w] : x_up[w];
+            uint32_t nw = nw_n, hw = hw_n;
+            if (t + 1 < T) fetch(c + 1);
             uint32_t bot[4 * SW];
 #pragma unroll
             for (int w = 0; w < 4 * SW; ++w) bot[w] = 0;
@@ -460,12 +483,17 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
                     top[4 * w + 2] = tc[w].z;
                     top[4 * w + 3] = tc[w].w;
                 }
+                auto code_of = [&](int k) -> uint32_t {
+                    const int nb = REV ? 7 - k : k;
+                    return ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
+                };
+                uint32_t w[R / 4];
+                load_profile<R>(prof_lane, code_of(0), w);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const int nb = REV ? 7 - k : k;
-                    const uint32_t code = ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
-                    uint32_t w[R / 4];
-                    load_profile<R>(prof_lane, code, w);
+                    uint32_t wn[R / 4];
+                    if (k < 7) load_profile<R>(prof_lane, code_of(k + 1), wn);
+                    __builtin_amdgcn_sched_barrier(0);
                     int htop, F;
                     uint32_t tag;
                     if constexpr (WIDE) {
@@ -484,6 +512,11 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
                         bot[2 * k + 1] = (uint32_t)F;
                     } else {
                         bot[k] = (uint32_t)H[R - 1] | ((uint32_t)F << 16);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (k < 7) {
+#pragma unroll
+                        for (int i = 0; i < R / 4; ++i) w[i] = wn[i];
                     }
                 }
             }
@@ -860,8 +893,8 @@ static hipError_t launch_persistent_r(const Args& a, int grid, hipStream_t strea
 hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream)
 {
     switch (a.rows_per_lane) {
+    case 8: return launch_persistent_r<8>(a, grid, stream);
     case 16: return launch_persistent_r<16>(a, grid, stream);
-    case 32: return launch_persistent_r<32>(a, grid, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -882,8 +915,8 @@ static hipError_t launch_plain_r(const Args& a, int kind, int first, int count, 
 hipError_t launch_plain(const Args& a, int kind, int first, int count, int grid, hipStream_t stream)
 {
     switch (a.rows_per_lane) {
+    case 8: return launch_plain_r<8>(a, kind, first, count, grid, stream);
     case 16: return launch_plain_r<16>(a, kind, first, count, grid, stream);
-    case 32: return launch_plain_r<32>(a, kind, first, count, grid, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -903,7 +936,7 @@ static hipError_t set_attrs_r()
 hipError_t set_kernel_attributes()
 {
     hipError_t e = set_attrs_r<16>();
-    return e == hipSuccess ? set_attrs_r<32>() : e;
+    return e == hipSuccess ? set_attrs_r<8>() : e;
 }
 
 }  // namespace swk

@@ -147,7 +147,7 @@ def test_tuning_does_not_change_results(sw):
     ps = P.concat([P.config_small(), adversarial_set(3, 300, 1500)])
     ref = None
     try:
-        for R, im, bpc in [(16, 1024, 0), (32, 1024, 0), (16, 64, 0), (32, 256, 2), (16, 512, 1)]:
+        for R, im, bpc in [(16, 1024, 0), (8, 512, 0), (16, 64, 0), (8, 256, 2), (16, 512, 1), (8, 64, 3)]:
             sw.set_tuning(R, im, bpc)
             say("tuning R=%d inter_max=%d bpc=%d" % (R, im, bpc))
             got = gpu_align(sw, ps)
