@@ -394,6 +394,8 @@ class KmerIndex:
         """(query, reference, shared) with >= min_shared distinct shared k-mers,
         at most `top` references per query (most shared first)."""
         qk, qs = kmer_sets(q_asc, q_offs, self.k)
+        o = np.argsort(qk)  # sorted needles: numpy's binary search reuses the last bound
+        qk, qs = qk[o], qs[o]
         lo = np.searchsorted(self.km, qk, side="left")
         hi = np.searchsorted(self.km, qk, side="right")
         cnt = hi - lo
@@ -434,13 +436,27 @@ def serving(n_fam: int = 20000, per_fam: int = 50, n_batches: int = 200, max_bat
     ref, ref_o = mutate_many(rng, src, src_o, rng.uniform(0.2, 0.6, len(fam)), 0.03)
     index = KmerIndex(ref, ref_o)
     sizes = np.exp(rng.uniform(0.0, np.log(max_batch + 1), n_batches)).astype(np.int64).clip(1, max_batch)
-    batches = []
-    for b in range(n_batches):
-        r2 = rng_for(6, seed * 100003 + b)
-        f = r2.integers(0, n_fam, int(sizes[b]))
-        s2 = anc[gather_segments(anc_o[f], La[f])]
-        s2o = np.concatenate([[0], np.cumsum(La[f])])
-        q, qo = mutate_many(r2, s2, s2o, r2.uniform(0.2, 0.6, len(f)), 0.03)
-        qq, rr, _ = index.candidates(q, qo, 2, top)
-        batches.append((q, qo, np.stack([qq, rr], 1).astype(np.int32)))
+    global _SERVE_STATE
+    _SERVE_STATE = (anc, anc_o, La, n_fam, index, top)
+    try:
+        batches = _map_chunks(_serve_batch, [(seed, b, int(sizes[b])) for b in range(n_batches)], workers)
+    finally:
+        _SERVE_STATE = None
     return ServeWorkload(ref, ref_o, batches, sizes)
+
+
+_SERVE_STATE = None  # shared with the forked workers of serving()
+
+
+def _serve_batch(job):
+    """One query batch of serving(): fresh members of random families and
+    their candidate references (seeded by batch number)."""
+    seed, b, size = job
+    anc, anc_o, La, n_fam, index, top = _SERVE_STATE
+    r2 = rng_for(6, seed * 100003 + b)
+    f = r2.integers(0, n_fam, size)
+    s2 = anc[gather_segments(anc_o[f], La[f])]
+    s2o = np.concatenate([[0], np.cumsum(La[f])])
+    q, qo = mutate_many(r2, s2, s2o, r2.uniform(0.2, 0.6, len(f)), 0.03)
+    qq, rr, _ = index.candidates(q, qo, 2, top)
+    return (q, qo, np.stack([qq, rr], 1).astype(np.int32))
