@@ -42,6 +42,9 @@ def main():
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--inter-max", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--group16-max", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner on the workload before timing")
     ap.add_argument("--no-graph", action="store_true",
                     help="persistent form launched directly instead of replayed as a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -72,8 +75,8 @@ def main():
         serve_bench(args)
         return
     sw.lib()
-    if args.rows_per_lane or args.inter_max or args.blocks_per_cu:
-        sw.set_tuning(args.rows_per_lane, args.inter_max, args.blocks_per_cu)
+    if args.rows_per_lane or args.inter_max or args.blocks_per_cu or args.group16_max:
+        sw.set_tuning(args.rows_per_lane, args.inter_max, args.blocks_per_cu, args.group16_max)
     tuning = sw.get_tuning()
 
     t0 = time.time()
@@ -104,6 +107,15 @@ def main():
                               ctypes.c_void_p(out_d.data_ptr()), ctypes.c_void_p(sptr), flags)
         if rc:
             raise sw.SwError(rc, "sw_batch_align")
+
+    if args.autotune:
+        rc = L.sw_pack(ctypes.c_void_p(ascii_d.data_ptr()), n_res, ctypes.c_void_p(packed_d.data_ptr()),
+                       packed_d.numel(), ctypes.c_void_p(sptr))
+        if rc:
+            raise sw.SwError(rc, "sw_pack")
+        chosen, ms = sw.autotune(packed_d, offs_d, pairs_d, 11, 1, reps=2, out=out_d, stream=stream)
+        log("autotune chose %s (%.2f ms per call)" % (chosen, ms))
+        tuning = sw.get_tuning()
 
     def timed(flags, steps, warmup, label):
         for _ in range(warmup):

@@ -157,25 +157,27 @@ SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
  * Kernel shape used by later calls on the current device.  rows_per_lane is
  * the number of query rows each lane keeps in registers (8 or 16);
  * inter_max_len is the longest pair (max of both lengths, 64..1024, at most
- * 64 rows_per_lane) that is
- * aligned one pair per lane, longer pairs are spread over a group of 16 lanes
- * (up to 4096 residues) or a whole 64-lane wave;
- * blocks_per_cu sets the persistent grid (1..8).  Any field <= 0 keeps the
- * current value.  Results never depend on these values.
+ * 64 rows_per_lane) that is aligned one pair per lane; longer pairs up to
+ * group16_max_len (a power of two, 64..4096) are spread over a group of 16
+ * lanes, longer ones over a whole 64-lane wave; blocks_per_cu sets the
+ * persistent grid (1..8).  Any field <= 0 keeps the current value.  Results
+ * never depend on these values.
  */
 typedef struct {
     int32_t rows_per_lane;
     int32_t inter_max_len;
     int32_t blocks_per_cu;
+    int32_t group16_max_len;
 } sw_tuning;
 SW_API int sw_set_tuning(const sw_tuning* t);
 SW_API int sw_get_tuning(sw_tuning* t);
 
 /*
  * Autotuner: time sw_batch_align (persistent form) on this workload for every
- * candidate kernel shape (rows_per_lane 16/8, inter_max_len 256/512/1024 --
- * the length above which a pair gets a lane group instead of one lane --
- * and blocks_per_cu occupancy-derived or 2), `reps` timed runs each, require
+ * candidate kernel shape (rows_per_lane 16/8, inter_max_len 512/768/1024 --
+ * the length above which a pair gets a lane group instead of one lane --,
+ * group16_max_len 1024/2048/4096, blocks_per_cu occupancy-derived), `reps`
+ * timed runs each, require
  * every shape to give byte-identical results, keep the fastest as the current
  * tuning and report it in *chosen (and its time per call in *best_ms, may be
  * NULL).  Synchronises `stream`; out_dev receives the results.  On error the
@@ -196,15 +198,19 @@ SW_API int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters);
 /* ------------------------------------------------------------------ serving
  * Continuous batching against a reference set resident in HBM.  The server
  * keeps `max_slots` HIP streams, each with its own alignment workspace, and an
- * arena of hbm_budget_bytes for the device state of requests in flight
- * (query ASCII, packed queries, offsets, candidate pairs, results; see
- * sw_server_request_bytes).  A request is admitted when a slot is free and
- * its state fits in the part of the arena not in use; admitted requests run
- * concurrently, so work from a request that arrives while others are on the
- * GPU overlaps with theirs.  Results of a request do not depend on what else
- * is in flight.  The reference buffers (from sw_pack) stay owned by the
- * caller and must outlive the server.  Servers are not shareable between
- * devices; calls on one server are serialised by the server.
+ * arena of hbm_budget_bytes for the device state of admitted requests (query
+ * ASCII, packed queries, offsets, candidate pairs, results; see
+ * sw_server_request_bytes).  A request is admitted when its state fits in the
+ * part of the budget not held by earlier unfinished requests; admitted
+ * requests queue in arrival order, and whenever a slot is free all queued
+ * requests (up to 2^24 pairs) are merged into one launch on it.  A request
+ * that arrives while the device is busy therefore joins the next launch, and
+ * launches on different slots overlap.  Completions are collected and new
+ * launches started inside submit, poll, wait and stats.  Results of a request
+ * do not depend on what else is in flight.  The reference buffers (from
+ * sw_pack) stay owned by the caller and must outlive the server.  Servers are
+ * not shareable between devices; calls on one server are serialised by the
+ * server.
  */
 typedef struct sw_server sw_server;
 
@@ -214,26 +220,30 @@ SW_API int sw_server_create(const void* refs_packed_dev, const int64_t* ref_offs
                             const sw_scoring* scoring, size_t hbm_budget_bytes, int max_slots,
                             sw_server** server);
 
-/* Submit n_q query sequences (host ASCII, host int64 offsets[n_q + 1]) with
- * n_cand candidate pairs (host int32 [query index within the request,
- * reference index]).  On SW_OK *ticket identifies the request and out_host
- * (host, n_cand results) is written when the request completes (poll/wait);
- * the library copies the inputs before returning.  SW_EAGAIN: no free slot
- * or not enough free budget now, retry after a completion.  SW_ENOMEM: the
- * request can never fit the budget.  SW_ECANCELED after destroy began. */
+/* Submit n_q query sequences (host ASCII, host int64 offsets[n_q + 1] with
+ * offsets[0] == 0) with n_cand candidate pairs (host int32 [query index within
+ * the request, reference index]).  On SW_OK *ticket identifies the request and
+ * out_host (host, n_cand results) is written when the request completes
+ * (poll/wait); the library copies the inputs before returning.  SW_EAGAIN: not
+ * enough free budget now, retry after a completion.  SW_ENOMEM: the request
+ * can never fit the budget.  SW_ERANGE: a query index outside [0, n_q), or
+ * more than 2^24 pairs.  SW_ECANCELED after destroy began.  A reference index
+ * outside the resident set gives score -1 for that pair. */
 SW_API int sw_server_submit(sw_server* server, const char* q_ascii, const int64_t* q_offsets, int64_t n_q,
                             const int32_t* cand, int64_t n_cand, sw_result* out_host, uint64_t* ticket);
 
 /* SW_OK once the request is complete (results copied, resources freed; the
- * ticket is then retired), SW_EAGAIN while it runs, SW_EINVAL for an unknown
- * ticket. */
+ * ticket is then retired), SW_EAGAIN while it waits or runs, SW_EINVAL for an
+ * unknown ticket; a launch that failed returns its error (SW_EDEVICE,
+ * SW_ENOMEM) for each of its requests. */
 SW_API int sw_server_poll(sw_server* server, uint64_t ticket);
 
 /* Poll until complete or until timeout_us elapses (SW_ETIMEOUT); a negative
  * timeout waits without limit. */
 SW_API int sw_server_wait(sw_server* server, uint64_t ticket, int64_t timeout_us);
 
-/* Requests in flight, arena bytes in use and the budget (any pointer may be NULL). */
+/* Requests admitted and not complete, budget bytes they hold and the budget
+ * (any pointer may be NULL). */
 SW_API int sw_server_stats(sw_server* server, int64_t* inflight, int64_t* bytes_in_use, int64_t* budget);
 
 /* Arena bytes a request of this size needs (0 for negative arguments). */

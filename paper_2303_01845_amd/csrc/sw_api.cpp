@@ -49,7 +49,7 @@ int ceil_log2(int64_t x)
     return b;
 }
 
-Ordering make_ordering(int R, int inter_max)
+Ordering make_ordering(int R, int inter_max, int group16_max)
 {
     struct Key {
         int cell;
@@ -77,7 +77,7 @@ Ordering make_ordering(int R, int inter_max)
         for (int cb = 0; cb < kWideCostBins; ++cb) {
             Key k;
             k.cell = kInterCells + b * kWideCostBins + cb;
-            k.kind = ((int64_t)1 << b) <= kMaxP16Len ? 16 : 64;
+            k.kind = ((int64_t)1 << b) <= std::min(group16_max, kMaxP16Len) ? 16 : 64;
             k.bucket = b;
             k.cost = cb;
             k.s = k.c = 0;
@@ -124,14 +124,14 @@ struct GraphKey {
     int64_t n_pairs;
     int32_t go, ge;
     void* out;
-    int R, inter_max, grid;
+    int R, inter_max, group16_max, grid;
     int64_t slot_words;
     bool operator<(const GraphKey& o) const
     {
         return std::tie(q_packed, q_offsets, n_q, r_packed, r_offsets, n_r, pairs, n_pairs, go, ge, out, R,
-                        inter_max, grid, slot_words) <
+                        inter_max, group16_max, grid, slot_words) <
                std::tie(o.q_packed, o.q_offsets, o.n_q, o.r_packed, o.r_offsets, o.n_r, o.pairs, o.n_pairs, o.go,
-                        o.ge, o.out, o.R, o.inter_max, o.grid, o.slot_words);
+                        o.ge, o.out, o.R, o.inter_max, o.group16_max, o.grid, o.slot_words);
     }
 };
 
@@ -190,6 +190,7 @@ struct Device {
     int n_cu = 0;
     int R = 16;
     int inter_max = 1024;
+    int group16_max = kDefaultGroup16Max;
     int bpc_user = 0;  // 0: occupancy-derived
     Ordering ord;
     int32_t* rank_cell_persistent = nullptr;
@@ -204,7 +205,7 @@ std::map<int, std::unique_ptr<Device>> g_devices;
 
 int upload_ordering(Device& d)
 {
-    d.ord = make_ordering(d.R, d.inter_max);
+    d.ord = make_ordering(d.R, d.inter_max, d.group16_max);
     HIP_TRY(hipMemcpy(d.rank_cell_persistent, d.ord.rank_cell_persistent.data(), sizeof(int32_t) * kNumCells,
                       hipMemcpyHostToDevice),
             "upload ordering");
@@ -432,6 +433,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     a.ge = scoring->gap_extend;
     a.rows_per_lane = d.R;
     a.inter_max_len = d.inter_max;
+    a.group16_max_len = d.group16_max;
 
     const bool timed = flags & SW_TIMED;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -479,7 +481,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             HIP_TRY(end_timed(), "hipEventRecord");
         } else {
             GraphKey key{q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev,
-                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, grid, sw_words};
+                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, d.group16_max, grid, sw_words};
             auto it = w.graphs.find(key);
             if (it == w.graphs.end()) {
                 if (w.graphs.size() >= 16) {
@@ -559,6 +561,9 @@ int sw_set_tuning(const sw_tuning* t)
         (t->inter_max_len + t->rows_per_lane - 1) / t->rows_per_lane > kMaxInterStrips)
         return SW_EINVAL;
     if (t->blocks_per_cu > 8) return SW_EINVAL;
+    if (t->group16_max_len > 0 && (t->group16_max_len < 64 || t->group16_max_len > kMaxP16Len ||
+                                   (t->group16_max_len & (t->group16_max_len - 1)) != 0))
+        return SW_EINVAL;
     std::lock_guard<std::mutex> lock(g_mutex);
     Device* d = nullptr;
     int rc = get_device(&d);
@@ -566,10 +571,12 @@ int sw_set_tuning(const sw_tuning* t)
     const int R = t->rows_per_lane > 0 ? t->rows_per_lane : d->R;
     const int im = t->inter_max_len > 0 ? t->inter_max_len : d->inter_max;
     if ((im + R - 1) / R > kMaxInterStrips) return SW_EINVAL;
-    const bool reorder = R != d->R || im != d->inter_max;
+    const int g16 = t->group16_max_len > 0 ? t->group16_max_len : d->group16_max;
+    const bool reorder = R != d->R || im != d->inter_max || g16 != d->group16_max;
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     d->R = R;
     d->inter_max = im;
+    d->group16_max = g16;
     if (t->blocks_per_cu > 0) d->bpc_user = t->blocks_per_cu;
     if (reorder) {
         rc = upload_ordering(*d);
@@ -589,6 +596,7 @@ int sw_get_tuning(sw_tuning* t)
     t->rows_per_lane = d->R;
     t->inter_max_len = d->inter_max;
     t->blocks_per_cu = blocks_per_cu(*d);
+    t->group16_max_len = d->group16_max;
     return SW_OK;
 }
 
@@ -610,13 +618,13 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
     int rc = sw_get_tuning(&orig);
     if (rc) return rc;
     struct Cand {
-        int R, im, bpc;
+        int R, im, bpc, g16;
     };
     std::vector<Cand> cands;
     for (int R : {16, 8})
-        for (int im : {256, 512, 1024})
-            for (int bpc : {0, 2})
-                if ((im + R - 1) / R <= kMaxInterStrips) cands.push_back({R, im, bpc});
+        for (int im : {512, 768, 1024})
+            for (int g16 : {1024, 2048, 4096})
+                if ((im + R - 1) / R <= kMaxInterStrips) cands.push_back({R, im, 0, g16});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
@@ -625,7 +633,7 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
     sw_tuning best_t = orig;
     bool have_ref = false;
     for (const Cand& c : cands) {
-        sw_tuning t{c.R, c.im, c.bpc};
+        sw_tuning t{c.R, c.im, c.bpc, c.g16};
         if (c.bpc == 0) {  // back to the occupancy-derived grid
             std::lock_guard<std::mutex> lock(g_mutex);
             Device* d = nullptr;
@@ -647,7 +655,8 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
             have_ref = true;
         } else if (std::memcmp(ref.data(), cur.data(), sizeof(sw_result) * (size_t)n_pairs) != 0) {
             std::snprintf(g_last_error, sizeof(g_last_error),
-                          "autotune: results differ between kernel shapes (R=%d inter_max=%d)", c.R, c.im);
+                          "autotune: results differ between kernel shapes (R=%d inter_max=%d group16_max=%d)",
+                          c.R, c.im, c.g16);
             rc = SW_EDEVICE;
             break;
         }

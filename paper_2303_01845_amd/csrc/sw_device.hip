@@ -8,8 +8,8 @@
 // the same recurrence over the reversed prefixes (first reversed cell that
 // reaches S).  All arithmetic is exact int32.
 //
-// Cell update used everywhere (8-9 VALU instructions per cell):
-//   d  = H[i-1][j-1] + s(q_i, r_j)           one SDWA add (profile byte, sign-extended)
+// Cell update of the int32 paths (about 10 VALU instructions per cell):
+//   d  = H[i-1][j-1] + s(q_i, r_j)           profile nibble (v_bfe) + add3 with -bias
 //   H  = max3(d, E[i][j], F[i][j])           E, F >= 0, so H >= 0 is the local floor
 //   hg = sat(H - go)                         v_sub_u32 clamp
 //   E[i][j+1] = max(E[i][j] - ge, hg)        hg >= 0 keeps E >= 0
@@ -18,15 +18,20 @@
 // Keeping E and F saturated at 0 leaves H exactly as in the textbook
 // recurrence: by induction E_sat = max(E, 0), and H only uses max(0, E).
 //
-// Kernel body: one pair per lane.  The lane keeps R query rows in registers
-// and sweeps the reference; horizontal strips of R rows hand their bottom row
-// to the next strip through a per-block scratch slot; the substitution scores
-// come from a per-lane query profile in LDS.  Two variants: "narrow" for
-// pairs whose scores fit 16 bits (one dword per boundary cell, 16-bit column
-// tags) and "wide" for any pair up to the length limit (two dwords per
-// boundary cell, 12-bit column tags folded every 4096 columns).
+// Work decomposition.  Pairs up to 1024 residues get one lane each, longer
+// ones up to 4096 a group of 16 lanes, longer still a whole wave.  A lane
+// keeps R query rows in registers and sweeps the reference in chunks of 8
+// columns; a group of P lanes covers a super-strip of P R rows as a
+// wavefront, and super-strips hand their bottom row to the next one through a
+// per-block scratch slot.  Scores come from a per-lane query profile in LDS.
+// The one- and 16-lane paths first run a packed 16-bit pass (two cells per
+// instruction) that only finds the best score and the super-strip holding its
+// first cell, then recompute that super-strip in int32 with cell trackers;
+// the whole-wave path ("wide": any length, two dwords per boundary cell,
+// 12-bit column tags folded every 4096 columns) runs in int32 throughout.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sw_internal.h"
 
@@ -73,9 +78,12 @@ static constexpr int ncbi_index(char c)
     return -1;
 }
 
+// Offset that makes every BLOSUM62 score non-negative (the minimum is -4).
+constexpr int kScoreBias = 4;
+
 struct CodeTables {
-    uint32_t tab[kNumCodes][8];  // row c: bytes s(c, x) for x = 0..31 (pad and unused: -128)
-    uint8_t ascii[256];          // ASCII -> code, 0xFF if not a symbol
+    uint32_t tabb[kNumCodes][8];  // row c: bytes s(c, x) + kScoreBias for x = 0..31 (pad and unused: 0)
+    uint8_t ascii[256];           // ASCII -> code, 0xFF if not a symbol
 };
 
 static constexpr CodeTables make_tables()
@@ -83,15 +91,15 @@ static constexpr CodeTables make_tables()
     CodeTables t{};
     for (int a = 0; a < kNumCodes; ++a)
         for (int w = 0; w < 8; ++w) {
-            uint32_t word = 0;
+            uint32_t wordb = 0;
             for (int k = 0; k < 4; ++k) {
                 int b = 4 * w + k;
-                int v = -128;
+                int vb = 0;
                 if (a < kNumSym && b < kNumSym)
-                    v = kBlosum62Ncbi[ncbi_index(kCodeOrder[a])][ncbi_index(kCodeOrder[b])];
-                word |= (uint32_t)(uint8_t)(int8_t)v << (8 * k);
+                    vb = kBlosum62Ncbi[ncbi_index(kCodeOrder[a])][ncbi_index(kCodeOrder[b])] + kScoreBias;
+                wordb |= (uint32_t)(uint8_t)vb << (8 * k);
             }
-            t.tab[a][w] = word;
+            t.tabb[a][w] = wordb;
         }
     for (int c = 0; c < 256; ++c) t.ascii[c] = 0xFF;
     for (int a = 0; a < kNumSym; ++a) t.ascii[(unsigned char)kCodeOrder[a]] = (uint8_t)a;
@@ -182,23 +190,20 @@ __device__ __forceinline__ void row_codes(const SeqView& qv, int row0, int M, ui
 }
 
 // ------------------------------------------------------------------ query profile in LDS
-// Layout [code][lane][R bytes]: lane l's scores for its R rows against a
-// reference residue `code` are 8 or 16 contiguous bytes; a wave's reads of
-// one row of the layout are contiguous in lane order, so the 8- or 16-byte
-// reads are conflict-free whatever codes the lanes hold.
+// Layout [code][lane][R/2 bytes]: lane l's scores for its R rows against a
+// reference residue `code`, plus kScoreBias so that each fits 4 bits (BLOSUM62
+// spans -4..11), padding 0.  Dword j of an entry holds rows 4j .. 4j+3 in its
+// low half and rows 4(j + R/8) .. in its high half, one nibble per row in row
+// order: for R = 16, dword 0 = rows 0-3 | 8-11 and dword 1 = rows 4-7 | 12-15,
+// so the packed pass finds the rows of both halves of a register pair in the
+// same bit positions.  A wave's reads of one row of the layout are contiguous
+// in lane order, so the 4- or 8-byte reads are conflict-free whatever codes
+// the lanes hold.  At 8 bytes per lane and code (R = 16) the profile takes
+// 12.8 KB per wave, which leaves room for two waves per SIMD.
+constexpr int prof_bytes(int R) { return R / 2; }
 
-// One profile entry (R bytes) as 16-byte stores, or one 8-byte store for R = 8.
-template <int R>
-__device__ __forceinline__ void store_entry(uint8_t* dst, const uint32_t (&v)[R / 4])
-{
-    if constexpr (R == 8) {
-        *reinterpret_cast<uint2*>(dst) = make_uint2(v[0], v[1]);
-    } else {
-        uint4* d4 = reinterpret_cast<uint4*>(dst);
-#pragma unroll
-        for (int w = 0; w < R / 16; ++w) d4[w] = make_uint4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
-    }
-}
+// 4 bytes, each below 16, as 4 nibbles in the low 16 bits.
+__device__ __forceinline__ uint32_t nib4(uint32_t b) { return b | (b >> 4); }  // bytes 0 and 2 hold them
 
 template <int R>
 __device__ __forceinline__ void build_profile(uint8_t* prof, int lane, const uint32_t (&qc)[R])
@@ -219,52 +224,54 @@ __device__ __forceinline__ void build_profile(uint8_t* prof, int lane, const uin
         sel[w][1] = s1;
         sel[w][2] = s2;
     }
-    uint8_t* base = prof + lane * R;
+    uint8_t* base = prof + lane * prof_bytes(R);
 #pragma unroll 1
     for (int c = 0; c < kNumSym; ++c) {
-        const uint32_t* t = c_tables.tab[c];
+        const uint32_t* t = c_tables.tabb[c];
         const uint32_t t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3], t4 = t[4], t5 = t[5];
-        uint32_t v[R / 4];
+        uint32_t v[R / 4];  // rows 4w .. 4w+3, one byte each
 #pragma unroll
         for (int w = 0; w < R / 4; ++w)
-            v[w] = __builtin_amdgcn_perm(t1, t0, sel[w][0]) | __builtin_amdgcn_perm(t3, t2, sel[w][1]) |
-                   __builtin_amdgcn_perm(t5, t4, sel[w][2]);
-        store_entry<R>(base + c * (kWave * R), v);
+            v[w] = nib4(__builtin_amdgcn_perm(t1, t0, sel[w][0]) | __builtin_amdgcn_perm(t3, t2, sel[w][1]) |
+                        __builtin_amdgcn_perm(t5, t4, sel[w][2]));
+        uint8_t* dst = base + c * (kWave * prof_bytes(R));
+        // dword j: nibbles of row group j (low half) and j + R/8 (high half)
+        if constexpr (R == 8) {
+            *reinterpret_cast<uint32_t*>(dst) = __builtin_amdgcn_perm(v[1], v[0], 0x06040200u);
+        } else {
+            *reinterpret_cast<uint2*>(dst) = make_uint2(__builtin_amdgcn_perm(v[2], v[0], 0x06040200u),
+                                                        __builtin_amdgcn_perm(v[3], v[1], 0x06040200u));
+        }
     }
-    uint32_t pad[R / 4];
-#pragma unroll
-    for (int w = 0; w < R / 4; ++w) pad[w] = 0x80808080u;
-    store_entry<R>(base + kPadCode * (kWave * R), pad);
+    uint8_t* dst = base + kPadCode * (kWave * prof_bytes(R));
+    if constexpr (R == 8)
+        *reinterpret_cast<uint32_t*>(dst) = 0u;
+    else
+        *reinterpret_cast<uint2*>(dst) = make_uint2(0u, 0u);
 }
 
 template <int R>
-__device__ __forceinline__ void load_profile(const uint8_t* prof_lane, uint32_t code, uint32_t (&w)[R / 4])
+__device__ __forceinline__ void load_profile(const uint8_t* prof_lane, uint32_t code, uint32_t (&w)[R / 8])
 {
+    const uint8_t* p = prof_lane + code * (uint32_t)(kWave * prof_bytes(R));
     if constexpr (R == 8) {
-        const uint2 v = *reinterpret_cast<const uint2*>(prof_lane + code * (uint32_t)(kWave * R));
+        w[0] = *reinterpret_cast<const uint32_t*>(p);
+    } else {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
         w[0] = v.x;
         w[1] = v.y;
-        return;
     }
-    const uint4* p = reinterpret_cast<const uint4*>(prof_lane + code * (uint32_t)(kWave * R));
-#pragma unroll
-    for (int k = 0; k < R / 16; ++k) {
-        const uint4 v = p[k];
-        w[4 * k] = v.x;
-        w[4 * k + 1] = v.y;
-        w[4 * k + 2] = v.z;
-        w[4 * k + 3] = v.w;
-    }
+}
+
+// Biased score (0..15) of row r in a profile entry.
+template <int R, int r>
+__device__ __forceinline__ uint32_t nib_score(const uint32_t (&w)[R / 8])
+{
+    constexpr int grp = r >> 2, j = grp % (R / 8), half = grp / (R / 8);
+    return __builtin_amdgcn_ubfe(w[j], 16 * half + 4 * (r & 3), 4);
 }
 
 // ------------------------------------------------------------------ the cell update
-// h + sign_extend(byte SEL of w), one v_add_u32 with an SDWA byte operand.
-template <int SEL>
-__device__ __forceinline__ int add_sbyte(int h, uint32_t w)
-{
-    return h + (int)(int8_t)(uint8_t)(w >> (8 * SEL));
-}
-
 // Hides what the compiler knows about the value's range (no instruction).
 // E and F are never negative; once the compiler proves that, it splits
 // max(max(d, E), F) into a signed and an unsigned max instead of one
@@ -275,11 +282,11 @@ template <int R, int I>
 struct RowUnroll {
     template <int TB>
     static __device__ __forceinline__ void run(int (&H)[R], int (&E)[R], uint32_t (&K)[R],
-                                               const uint32_t (&w)[R / 4], int& d, int& F,
+                                               const uint32_t (&w)[R / 8], int& d, int& F,
                                                uint32_t tag, uint32_t go, int ge)
     {
         int dn = 0;
-        if constexpr (I + 1 < R) dn = add_sbyte<(I + 1) & 3>(H[I], w[(I + 1) >> 2]);
+        if constexpr (I + 1 < R) dn = H[I] + (int)nib_score<R, I + 1>(w) - kScoreBias;
         const int h = max(max(d, E[I]), F);
         H[I] = h;
         const int hg = (int)__builtin_elementwise_sub_sat((uint32_t)h, go);
@@ -297,10 +304,10 @@ struct RowUnroll {
 // F[row0][j] and leaves as F[row0+R][j].
 template <int R, int TB>
 __device__ __forceinline__ void column_step(int (&H)[R], int (&E)[R], uint32_t (&K)[R],
-                                            const uint32_t (&w)[R / 4], int hdiag, int& F,
+                                            const uint32_t (&w)[R / 8], int hdiag, int& F,
                                             uint32_t tag, uint32_t go, int ge)
 {
-    int d = add_sbyte<0>(hdiag, w[0]);
+    int d = hdiag + (int)nib_score<R, 0>(w) - kScoreBias;
     RowUnroll<R, 0>::template run<TB>(H, E, K, w, d, F, tag, go, ge);
 }
 
@@ -366,27 +373,41 @@ __device__ __forceinline__ Best group_best(Best b)
     return b;
 }
 
-template <int R, int P, bool REV, bool WIDE>
-__device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t* __restrict__ slot,
-                            int64_t Q0, int M, int64_t R0, int N, int target)
+// Words of one boundary-row buffer of a block slot for groups of P lanes
+// (narrow cells, layout [chunk][group][8 cells]); the packed pass rotates
+// three of them.
+__host__ __device__ constexpr int64_t boundary_buf_words(int P)
+{
+    return (P == 1 ? (int64_t)kMaxInterChunks : (int64_t)(kMaxP16Len / 8)) * (kWave / P) * 8;
+}
+
+// ONE: sweep only super-strip `one_ss` of each group (it may differ between
+// groups; -1 for none), reading its input row from boundary buffer `one_buf`
+// of the slot and writing nothing: the exact-cell pass after the packed
+// score pass.
+template <int R, int P, bool REV, bool WIDE, bool ONE = false>
+__device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t* __restrict__ slot,
+                            int64_t Q0, int M, int64_t R0, int N, int target, int one_ss = -1, int one_buf = 0)
 {
     constexpr int TB = WIDE ? 12 : 16;  // tag bits of the per-row trackers
     constexpr int SW = WIDE ? 4 : 2;    // uint4 per boundary chunk of 8 columns
     constexpr int G = kWave / P;        // groups per wave
     const int lane = threadIdx.x & (kWave - 1);
     const int u = lane % P, g = lane / P;
-    const uint8_t* prof_lane = prof + lane * R;
+    const uint8_t* prof_lane = prof + lane * prof_bytes(R);
     const uint32_t go = (uint32_t)a.go;
     const int ge = a.ge;
     Best b{0, -1, -1};  // this lane's rows only
-    const int my_ss = (M > 0 && N > 0) ? (M + P * R - 1) / (P * R) : 0;
+    const int all_ss = (M > 0 && N > 0) ? (M + P * R - 1) / (P * R) : 0;
+    const int my_ss = ONE ? (one_ss >= 0 && one_ss < all_ss ? 1 : 0) : all_ss;
     const int my_chunks = (N + 7) / 8;
     const int wss = uni(wave_max(my_ss));
     const int wc = uni(wave_max(my_ss > 0 ? my_chunks : 0));
-    bool done = my_ss == 0 || (REV && target <= 0);
+    bool done = my_ss == 0 || (REV && target <= 0 && !ONE);
     const SeqView qv = seq_view(a.qblk, Q0);
     const SeqView rv = seq_view(a.rblk, R0);
-    uint4* slot4 = reinterpret_cast<uint4*>(slot) + SW * g;
+    uint4* slot4 = reinterpret_cast<uint4*>(slot + (ONE ? (int64_t)min(max(one_buf, 0), 2) * boundary_buf_words(P) : 0)) +
+                   SW * g;
     uint4* x_mine = xbuf + SW * lane;
     const uint4* x_up = xbuf + SW * (lane > 0 ? lane - 1 : 0);
 
@@ -394,7 +415,8 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
     for (int ss = 0; ss < wss; ++ss) {
         if (__ballot(!done && ss < my_ss) == 0) break;
         const bool gact = !done && ss < my_ss;
-        const int row0 = ss * P * R + u * R;
+        const int sv = ONE ? one_ss : ss;  // super-strip index
+        const int row0 = sv * P * R + u * R;
         {
             uint32_t qc[R];
             row_codes<R, REV>(qv, gact ? row0 : M, M, qc);
@@ -409,8 +431,8 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
             K[r] = 0;
         }
         int hdiag = 0;
-        const bool read_top = ss > 0;            // uniform
-        const bool write_next = ss + 1 < my_ss;  // uniform within the group
+        const bool read_top = sv > 0;                    // uniform within the group
+        const bool write_next = !ONE && ss + 1 < my_ss;  // uniform within the group
 
         // wide: fold the 4096-column trackers into this lane's (score, row,
         // column), score descending, then row, then column ascending.  Tags
@@ -441,11 +463,12 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
         uint4 tc_n[SW];
         uint32_t nw_n, hw_n;
         auto fetch = [&](int cn) {
-            if (u == 0) {
-                const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
+            // load, then select (a select of addresses would become a flat load)
+            const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
 #pragma unroll
-                for (int w = 0; w < SW; ++w)
-                    tc_n[w] = read_top ? slot4[cc * G * SW + w] : make_uint4(0, 0, 0, 0);
+            for (int w = 0; w < SW; ++w) {
+                const uint4 v = slot4[cc * G * SW + w];
+                tc_n[w] = (u == 0 && read_top) ? v : make_uint4(0, 0, 0, 0);
             }
             window8(rv, chunk_x(cn), nw_n, hw_n);
         };
@@ -487,11 +510,11 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
                     const int nb = REV ? 7 - k : k;
                     return ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
                 };
-                uint32_t w[R / 4];
+                uint32_t w[R / 8];
                 load_profile<R>(prof_lane, code_of(0), w);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    uint32_t wn[R / 4];
+                    uint32_t wn[R / 8];
                     if (k < 7) load_profile<R>(prof_lane, code_of(k + 1), wn);
                     __builtin_amdgcn_sched_barrier(0);
                     int htop, F;
@@ -516,7 +539,7 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
                     __builtin_amdgcn_sched_barrier(0);
                     if (k < 7) {
 #pragma unroll
-                        for (int i = 0; i < R / 4; ++i) w[i] = wn[i];
+                        for (int i = 0; i < R / 8; ++i) w[i] = wn[i];
                     }
                 }
             }
@@ -559,6 +582,266 @@ __device__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t*
     return group_best<P>(b);
 }
 
+// ------------------------------------------------------------------ packed 16-bit score pass
+// Groups of P lanes per pair (P = 1 or 16) with 16 rows per lane, two cells
+// per 32-bit register: lane u of a group holds rows 16 P ss + 16 u + 0..7
+// (half A) in the low 16 bits and rows + 8..15 (half B) in the high 16 bits,
+// and B runs one column behind A, so at each step A updates column t and B
+// column t - 1 and every packed instruction does two cells of the recurrence.
+// As in group_sweep, lane u processes chunk c = t - u at iteration t; its A
+// half needs the bottom row of lane u - 1 (from the slot for u = 0), whose
+// columns 8c .. 8c+6 were finished in the previous iteration and column
+// 8c + 7 in the first step of this one, handed over in the middle of the
+// iteration.  Scores carry kScoreBias (pad 0, i.e. -4), the diagonal term is
+// sat(Hdiag + s + bias - bias), and E, F and hg saturate at 0 as in the int32
+// path, so real cells get the int32 values exactly.  Narrow cells (both
+// lengths <= 4096) keep every value below 11 * 4096 + 15 < 2^16.  Padding rows
+// and columns only hold values below the pair's maximum, so they cannot change
+// the best score or which super-strip first reaches it.
+//
+// The pass keeps per row a running maximum only.  Forward: the pair's best
+// score and the first super-strip that reaches it, whose input boundary row is
+// kept by rotating three boundary buffers; REV: the first super-strip whose
+// maximum reaches `target`, its input row still in the buffer it was read
+// from.  group_sweep<ONE> then recomputes that one super-strip in int32 with
+// cell trackers.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+// Keeps the compiler from moving memory accesses across this point (LDS
+// hand-over between lanes of one wave; the hardware keeps a wave's LDS
+// accesses in order).
+__device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
+
+struct StripPick {
+    int s;    // forward: best score (0 if none)
+    int ss;   // super-strip to recompute, -1 if none
+    int buf;  // boundary buffer holding its input row
+};
+
+template <int P, bool REV>
+__device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, uint32_t* xw, uint32_t* __restrict__ slot,
+                                  int64_t Q0, int M, int64_t R0, int N, int target)
+{
+    constexpr int G = kWave / P;
+    constexpr int64_t BW = boundary_buf_words(P);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int u = lane % P, g = lane / P;
+    const uint8_t* prof_lane = prof + lane * prof_bytes(16);
+    const unsigned short go16 = (unsigned short)min(a.go, 65535), ge16 = (unsigned short)min(a.ge, 65535);
+    const u16x2 go2 = {go16, go16}, ge2 = {ge16, ge16};
+    const u16x2 bias2 = {(unsigned short)kScoreBias, (unsigned short)kScoreBias};
+    const int my_ss = (M > 0 && N > 0) ? (M + 16 * P - 1) / (16 * P) : 0;
+    const int my_chunks = (N + 7) / 8;
+    const int wss = uni(wave_max(my_ss));
+    const int wc = uni(wave_max(my_ss > 0 ? my_chunks : 0));
+    bool done = my_ss == 0 || (REV && target <= 0);
+    const SeqView qv = seq_view(a.qblk, Q0);
+    const SeqView rv = seq_view(a.rblk, R0);
+    uint32_t* grp_slot = slot + 8 * g;  // [buffer][chunk][group][8 cells]
+    // hand-over between lanes: 8 words per lane at the end of an iteration
+    // (7 used) and one word in the middle
+    uint32_t* x_end = xw + 8 * lane;
+    const uint32_t* x_end_up = xw + 8 * (lane > 0 ? lane - 1 : 0);
+    uint32_t* x_mid = xw + 8 * kWave + lane;
+    const uint32_t* x_mid_up = xw + 8 * kWave + (lane > 0 ? lane - 1 : 0);
+    int bi = 0, bo = 1, bk = 2;  // boundary buffers: input, output, kept (uniform in a group)
+    StripPick pick{0, -1, 0};
+    auto chunk_x = [&](int c) __attribute__((always_inline)) -> int { return (c < 0 || 8 * c >= N) ? 0 : (REV ? -8 * c - 7 : 8 * c); };
+
+#pragma unroll 1
+    for (int ss = 0; ss < wss; ++ss) {
+        if (__ballot(!done && ss < my_ss) == 0) break;
+        const bool gact = !done && ss < my_ss;
+        const int row0 = ss * 16 * P + 16 * u;
+        {
+            uint32_t qc[16];
+            row_codes<16, REV>(qv, gact ? row0 : M, M, qc);
+            build_profile<16>(prof, lane, qc);
+        }
+        const bool read_top = ss > 0;
+        const bool write_next = ss + 1 < my_ss;
+        const uint4* in4 = reinterpret_cast<const uint4*>(grp_slot + bi * BW);
+        uint4* out4 = reinterpret_cast<uint4*>(grp_slot + bo * BW);
+        uint32_t H[8], E[8], Mx[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) H[i] = E[i] = Mx[i] = 0;
+        uint32_t up_prev = 0, fo_prev = 0, pw0 = 0, pw1 = 0;  // previous profile entry
+        uint32_t botp[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) botp[k] = 0;
+        uint4 tn0 = make_uint4(0, 0, 0, 0), tn1 = make_uint4(0, 0, 0, 0);
+        uint32_t nw_n, hw_n;
+        auto fetch = [&](int cn) __attribute__((always_inline)) {
+            // load from an index inside the pair's chunks, then select: the
+            // address is always valid and no select of addresses arises
+            const bool real = u == 0 && read_top && cn >= 0 && cn < my_chunks;
+            const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
+            const uint4 v0 = in4[cc * (G * 2)], v1 = in4[cc * (G * 2) + 1];
+            tn0 = real ? v0 : make_uint4(0, 0, 0, 0);
+            tn1 = real ? v1 : make_uint4(0, 0, 0, 0);
+            window8(rv, chunk_x(cn), nw_n, hw_n);
+        };
+        fetch(-u);
+        // Iteration t: lane u on chunk c = t - u, A on columns 8c .. 8c+7,
+        // B on 8c-1 .. 8c+6.  Each lane needs my_chunks + 1 chunk iterations
+        // (the last one for B's final column); the very last iteration of the
+        // wave has a single step.
+        auto iteration = [&](int t, auto steps_tag) __attribute__((always_inline)) {
+            constexpr int STEPS = decltype(steps_tag)::value;
+            const int c = t - u;
+            const bool act = gact && c >= 0 && c <= my_chunks;
+            uint32_t top[8] = {tn0.x, tn0.y, tn0.z, tn0.w, tn1.x, tn1.y, tn1.z, tn1.w};
+            if constexpr (P > 1) {
+                // both sources are read and the values selected (a select of
+                // addresses would turn into flat loads)
+                const uint4 e0 = reinterpret_cast<const uint4*>(x_end_up)[0];
+                const uint4 e1 = reinterpret_cast<const uint4*>(x_end_up)[1];
+                const bool up = u > 0;
+                top[0] = up ? e0.x : top[0];
+                top[1] = up ? e0.y : top[1];
+                top[2] = up ? e0.z : top[2];
+                top[3] = up ? e0.w : top[3];
+                top[4] = up ? e1.x : top[4];
+                top[5] = up ? e1.y : top[5];
+                top[6] = up ? e1.z : top[6];
+            }
+            uint32_t nw = nw_n, hw = hw_n;
+            if (t + 1 <= wc + P - 1) fetch(c + 1);
+            uint32_t bq[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) bq[k] = 0;
+            const int valid = min(max(N - 8 * c, 0), 8);
+            if (valid < 8) {
+                if (REV) {
+                    const uint32_t m4 = valid == 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu >> (4 * valid));
+                    nw = (nw & ~m4) | (0x88888888u & m4);
+                    hw |= 0xFFu >> valid;
+                } else {
+                    const uint32_t m4 = 0xFFFFFFFFu << (4 * valid);
+                    nw = (nw & ~m4) | (0x88888888u & m4);
+                    hw |= (0xFFu << valid) & 0xFFu;
+                }
+            }
+            auto code_of = [&](int k) __attribute__((always_inline)) -> uint32_t {
+                const int nb = REV ? 7 - k : k;
+                return ((nw >> (4 * nb)) & 15u) | (((hw >> nb) & 1u) << 4);
+            };
+            uint32_t w[2], wn[2];
+            // one step: A on column 8c + k, B on column 8c + k - 1
+            auto step = [&](int k) __attribute__((always_inline)) {
+                if (k + 1 < STEPS) load_profile<16>(prof_lane, code_of(k + 1), wn);
+                // low halves from this column's entry (A rows), high halves
+                // from the previous one (B rows): register i gets nibble i & 3
+                // of both
+                const uint32_t x0 = (pw0 & 0xFFFF0000u) | (w[0] & 0xFFFFu);
+                const uint32_t x1 = (pw1 & 0xFFFF0000u) | (w[1] & 0xFFFFu);
+                uint32_t sw[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sw[i] = ((i < 4 ? x0 : x1) >> (4 * (i & 3))) & 0x000F000Fu;
+                // row 0 inputs: A from the row above at column t, B from A's
+                // row 7 at column t - 1
+                const uint32_t up_cur = __builtin_amdgcn_perm(H[7], top[k], 0x05040100u);
+                uint32_t Fv = __builtin_amdgcn_perm(fo_prev, top[k], 0x05040302u);
+                uint32_t hd = up_prev;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const u16x2 d = __builtin_elementwise_sub_sat(as_u16x2(hd) + as_u16x2(sw[i]), bias2);
+                    const u16x2 h =
+                        __builtin_elementwise_max(__builtin_elementwise_max(d, as_u16x2(E[i])), as_u16x2(Fv));
+                    hd = H[i];
+                    H[i] = as_u32(h);
+                    const u16x2 hg = __builtin_elementwise_sub_sat(h, go2);
+                    E[i] = as_u32(__builtin_elementwise_max(__builtin_elementwise_sub_sat(as_u16x2(E[i]), ge2), hg));
+                    Fv = as_u32(__builtin_elementwise_max(__builtin_elementwise_sub_sat(as_u16x2(Fv), ge2), hg));
+                    Mx[i] = as_u32(__builtin_elementwise_max(as_u16x2(Mx[i]), h));
+                }
+                fo_prev = Fv;
+                up_prev = up_cur;
+                // B's row 15 at column t - 1 as (H | F << 16)
+                bq[k] = __builtin_amdgcn_perm(Fv, H[7], 0x07060302u);
+                pw0 = w[0];
+                pw1 = w[1];
+                w[0] = wn[0];
+                w[1] = wn[1];
+            };
+            if (act) {
+                load_profile<16>(prof_lane, code_of(0), w);
+                step(0);
+            }
+            if (P > 1) {
+                *x_mid = bq[0];  // column 8c - 1, for lane u + 1's chunk c - 1
+                mem_order();
+            }
+            if (act) {
+#pragma unroll
+                for (int k = 1; k < STEPS; ++k) {
+                    if (P > 1 && k == 7) {
+                        // column 8c + 7 of the row above, finished by lane
+                        // u - 1 in its first step of this iteration
+                        const uint32_t xm = *x_mid_up;
+                        top[7] = u > 0 ? xm : top[7];
+                    }
+                    step(k);
+                }
+            }
+            if (P > 1) {
+                // columns 8c .. 8c+6 for lane u + 1's next iteration
+                mem_order();
+                reinterpret_cast<uint4*>(x_end)[0] = make_uint4(bq[1], bq[2], bq[3], bq[4]);
+                reinterpret_cast<uint4*>(x_end)[1] = make_uint4(bq[5], bq[6], bq[7], 0u);
+                mem_order();
+            }
+            // chunk c-1 of the bottom row is complete: columns 8c-8 .. 8c-2
+            // from the previous iteration, 8c-1 from this one
+            if (u == P - 1 && act && write_next && c >= 1 && c - 1 < my_chunks) {
+                out4[(c - 1) * (G * 2)] = make_uint4(botp[1], botp[2], botp[3], botp[4]);
+                out4[(c - 1) * (G * 2) + 1] = make_uint4(botp[5], botp[6], botp[7], bq[0]);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) botp[k] = bq[k];
+        };
+        const int T = wc + P;  // iterations 0 .. wc + P - 1
+#pragma unroll 1
+        for (int t = 0; t < T - 1; ++t) iteration(t, std::integral_constant<int, 8>());
+        iteration(T - 1, std::integral_constant<int, 1>());
+        block_fence();
+        uint32_t m2 = Mx[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) m2 = as_u32(__builtin_elementwise_max(as_u16x2(m2), as_u16x2(Mx[i])));
+        int smax = (int)max(m2 & 0xFFFFu, m2 >> 16);
+#pragma unroll
+        for (int o = 1; o < P; o <<= 1) smax = max(smax, __shfl_xor(smax, o, kWave));
+        if (gact) {
+            if (REV) {
+                if (smax >= target) {
+                    pick.ss = ss;
+                    pick.buf = bi;
+                    done = true;
+                } else {
+                    const int tt = bi;
+                    bi = bo;
+                    bo = tt;
+                }
+            } else if (smax > pick.s) {
+                pick.s = smax;
+                pick.ss = ss;
+                pick.buf = bi;
+                const int tt = bk;
+                bk = bi;
+                bi = bo;
+                bo = tt;
+            } else {
+                const int tt = bi;
+                bi = bo;
+                bo = tt;
+            }
+        }
+    }
+    return pick;
+}
+
 // ------------------------------------------------------------------ per-item drivers
 __device__ __forceinline__ void write_result(sw_result* out, int pid, int S, int qs, int qe, int rs, int re)
 {
@@ -578,7 +861,7 @@ __device__ __forceinline__ void write_result(sw_result* out, int pid, int S, int
 
 // One work item: up to 64/P pairs, P lanes each.
 template <int R, int P, bool WIDE>
-__device__ void do_group(const Args& a, int first, int count, uint8_t* lds, uint32_t* slot)
+__device__ __forceinline__ void do_group(const Args& a, int first, int count, uint8_t* lds, uint32_t* slot)
 {
     constexpr int G = kWave / P;
     constexpr int SW = WIDE ? 4 : 2;
@@ -597,8 +880,12 @@ __device__ void do_group(const Args& a, int first, int count, uint8_t* lds, uint
         roff = a.r_offsets[ri];
         n = (int)(a.r_offsets[ri + 1] - roff);
         // the slot must hold one boundary cell per column for every group
+        // (narrow one- and 16-lane groups: three buffers of fixed size)
         const int64_t need = (int64_t)((n + 7) / 8) * G * SW * 4;
-        if (need > a.slot_words) {
+        const bool may_pack = R == 16 && (P == 64 ? max(m, n) <= kMaxP16Len : !WIDE);
+        const int max_chunks = P == 1 ? kMaxInterChunks : kMaxP16Len / 8;
+        if (need > a.slot_words ||
+            (may_pack && ((n + 7) / 8 > max_chunks || 3 * boundary_buf_words(P) > a.slot_words))) {
             if (u == 0) {
                 atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
                 sw_result bad;
@@ -610,7 +897,33 @@ __device__ void do_group(const Args& a, int first, int count, uint8_t* lds, uint
         }
     }
     uint8_t* prof = lds;
-    uint4* xbuf = reinterpret_cast<uint4*>(lds + kNumCodes * kWave * R);
+    uint4* xbuf = reinterpret_cast<uint4*>(lds + kNumCodes * kWave * prof_bytes(R));
+    // packed score passes for every pair up to kMaxP16Len residues (the one-
+    // and 16-lane groups only get such pairs; a whole wave takes the longest
+    // of them and everything beyond, which runs in int32 throughout), then the
+    // exact cells from one int32 super-strip each
+    bool packed = false;
+    if constexpr (R == 16) {
+        if constexpr (P == 64) packed = uni(max(m, n)) <= kMaxP16Len;  // one pair per item
+        else packed = !WIDE;
+    }
+    if (packed) {
+        uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
+        const StripPick pf = packed_sweep<P, false>(a, prof, xw, slot, qoff, m, roff, n, 0);
+        const Best f = group_sweep<R, P, false, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, pf.ss,
+                                                            pf.buf);
+        const bool has = f.s > 0;
+        const int64_t qr = qoff + (has ? f.i : 0), rr = roff + (has ? f.j : 0);
+        const int mr = has ? f.i + 1 : 0, nr = has ? f.j + 1 : 0;
+        const StripPick pr = packed_sweep<P, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+        const Best r = group_sweep<R, P, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s,
+                                                           has ? pr.ss : -1, pr.buf);
+        if (pid >= 0 && u == 0) {
+            if (f.s != pf.s || (has && r.s != f.s)) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+            write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
+        }
+        return;
+    }
     const Best f = group_sweep<R, P, false, WIDE>(a, prof, xbuf, slot, qoff, m, roff, n, 0);
     const bool has = f.s > 0;
     const Best r = group_sweep<R, P, true, WIDE>(a, prof, xbuf, slot, qoff + (has ? f.i : 0), has ? f.i + 1 : 0,
@@ -677,18 +990,32 @@ __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, uint32_t* _
     const int64_t p0 = 32 * t - kGuardRes;
     uint32_t nib[4] = {0, 0, 0, 0}, hib = 0;
     bool bad = false;
-    for (int k = 0; k < 32; ++k) {
-        const int64_t p = p0 + k;
-        uint32_t c = kPadCode;
-        if (p >= 0 && p < n) {
-            c = c_tables.ascii[ascii[p]];
-            if (c == 0xFFu) {
-                c = kPadCode;
-                bad = true;
-            }
+    auto put = [&](int k, uint32_t letter) {
+        uint32_t c = c_tables.ascii[letter];
+        if (c == 0xFFu) {
+            c = kPadCode;
+            bad = true;
         }
         nib[k >> 3] |= (c & 15u) << (4 * (k & 7));
         hib |= (c >> 4) << k;
+    };
+    if (p0 >= 0 && p0 + 32 <= n && ((reinterpret_cast<uintptr_t>(ascii) & 15u) == 0)) {
+        // interior word: two 16-byte loads instead of 32 byte loads
+        const uint4* src = reinterpret_cast<const uint4*>(ascii + p0);
+        const uint4 v0 = src[0], v1 = src[1];
+        const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+        for (int k = 0; k < 32; ++k) put(k, (w[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+    } else {
+        for (int k = 0; k < 32; ++k) {
+            const int64_t p = p0 + k;
+            if (p >= 0 && p < n) {
+                put(k, ascii[p]);
+            } else {
+                nib[k >> 3] |= (kPadCode & 15u) << (4 * (k & 7));
+                hib |= (kPadCode >> 4) << k;
+            }
+        }
     }
     const int64_t blkidx = t >> 3, sub = t & 7;  // 8 high words (256 residues) per block
     uint32_t* b = blk + blkidx * 40;
@@ -707,11 +1034,11 @@ __device__ __forceinline__ int ceil_log2(int64_t x)
 
 // Lanes per pair of a work cell: 1 for the short-pair cells, 16 for long
 // pairs up to kMaxP16Len residues, 64 beyond.
-__device__ __forceinline__ int cell_kind(int cell)
+__device__ __forceinline__ int cell_kind(int cell, int group16_max)
 {
     if (cell < kInterCells) return 1;
     const int bucket = (cell - kInterCells) / kWideCostBins;
-    return (1 << bucket) <= kMaxP16Len ? 16 : 64;
+    return (1 << bucket) <= min(group16_max, kMaxP16Len) ? 16 : 64;
 }
 
 // Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
@@ -792,7 +1119,7 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
         const int cell = a.rank_cell[rk];
         const int c = a.cell_count[cell];
         sum += c;
-        const int kind = cell_kind(cell);
+        const int kind = cell_kind(cell, a.group16_max_len);
         if (kind == 64) c64 += c;
         else if (kind == 16) c16 += c;
     }
@@ -836,15 +1163,15 @@ __global__ void k_scatter(Args a)
 }
 
 // ------------------------------------------------------------------ launchers
-size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * R + kXbufBytes; }
+size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * prof_bytes(R) + kXbufBytes; }
 
 int64_t slot_words()
 {
     // [chunk][group][8 cells]: 64 groups of one lane over at most 128 chunks
-    // (narrow), 4 groups over 512 chunks (16 lanes, narrow), 1 group over
-    // 8192 chunks (64 lanes, wide, two words per cell)
-    const int64_t p1 = (int64_t)kMaxInterChunks * 64 * 8;
-    const int64_t p16 = (int64_t)(kMaxP16Len / 8) * 4 * 8;
+    // (narrow, three buffers), 4 groups over 512 chunks (16 lanes, narrow), 1
+    // group over 8192 chunks (64 lanes, wide, two words per cell)
+    const int64_t p1 = 3 * boundary_buf_words(1);  // three boundary buffers of the packed pass
+    const int64_t p16 = 3 * boundary_buf_words(16);
     const int64_t p64 = (int64_t)((SW_MAX_SEQ_LEN + 7) / 8) * 1 * 16;
     return std::max(p1, std::max(p16, p64));
 }

@@ -44,7 +44,9 @@ constexpr int kWave = 64;
 constexpr int kMaxInterStrips = 64;    // ceil(inter_max_len / rows_per_lane) <= this
 constexpr int kMaxInterChunks = 128;   // ceil(inter_max_len / 8) <= this
 constexpr int kMaxInterLen = 1024;
-constexpr int kMaxP16Len = 4096;      // longer pairs get a whole wave
+constexpr int kMaxP16Len = 4096;      // longest pair a 16-lane group may get; the packed
+                                      // 16-bit pass also covers whole waves up to this
+constexpr int kDefaultGroup16Max = 2048;  // default group16_max_len
 constexpr int kXbufBytes = 64 * 64;   // LDS exchange buffer: 16 words per lane
 constexpr int kWideCostBins = 512;     // floor(16 * log2(m*n)) for long (wide) pairs
 constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
@@ -86,6 +88,7 @@ struct Args {
     int32_t go, ge;
     int32_t rows_per_lane;
     int32_t inter_max_len;
+    int32_t group16_max_len;   // longest pair of a 16-lane group (power of two)
 };
 
 // launchers (sw_device.hip); all asynchronous on `stream`

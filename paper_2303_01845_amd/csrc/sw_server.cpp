@@ -1,17 +1,21 @@
 // Continuous-batching server over a reference set resident in HBM.
 //
 // A request is a batch of query sequences (host ASCII) with a candidate list
-// of (query, reference) pairs.  It is admitted only when a slot (a HIP stream
-// with its own alignment workspace) is free and its in-flight device state
-// fits in what is left of the HBM budget; otherwise submit returns SW_EAGAIN
-// and the caller retries when an earlier request completes.  Admitted
-// requests run concurrently on their slots' streams: each one is copied in,
-// packed and aligned by one persistent launch against the resident set, and
-// its results are copied back; the persistent grids of different requests
-// share the compute units as their blocks drain.
+// of (query, reference) pairs.  It is admitted when its device state fits in
+// what is left of the HBM budget (otherwise submit returns SW_EAGAIN and the
+// caller retries after a completion); admitted requests queue in arrival
+// order.  Whenever a slot (a HIP stream with its own alignment workspace) is
+// free, every queued request is merged into one launch on it: the queries
+// are concatenated, copied in, packed and aligned against the resident set by
+// one persistent launch, and the results are copied back and handed to each
+// request.  Under load the launches grow, so the device stays busy; at low
+// load a request starts as soon as it arrives.  Launches on different slots
+// run concurrently.  Completions are found and new launches started inside
+// submit, poll, wait and stats.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -89,18 +93,30 @@ private:
 };
 
 struct Request {
-    uint64_t ticket = 0;
-    int slot = -1;
-    size_t dev_off = 0, dev_bytes = 0;
-    int64_t n_cand = 0;
+    int64_t n_q = 0, n_res = 0, n_cand = 0;
+    size_t reserved = 0;  // budget bytes held from admission to completion
+    std::vector<char> ascii;
+    std::vector<int64_t> offs;
+    std::vector<int32_t> cand;
     sw_result* out_host = nullptr;
-    sw_result* staged = nullptr;  // pinned, inside the slot's staging buffer
+    bool done = false;
+    int status = SW_OK;
+};
+
+// One launch: the requests merged into it, their device region and the
+// pinned results.
+struct Batch {
+    std::vector<uint64_t> tickets;
+    std::vector<int64_t> first;  // first result of each request
+    size_t dev_off = 0, dev_bytes = 0;
+    sw_result* staged = nullptr;
     hipEvent_t done = nullptr;
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     bool busy = false;
+    Batch batch;
     char* pinned = nullptr;  // staging for inputs and results
     size_t pinned_bytes = 0;
 };
@@ -114,14 +130,18 @@ struct sw_server {
     int64_t n_refs = 0;
     sw_scoring scoring{};
     Arena arena;
+    size_t reserved = 0;  // budget held by admitted, unfinished requests
     std::vector<Slot> slots;
-    std::map<uint64_t, Request> inflight;
+    std::map<uint64_t, Request> requests;  // admitted and not yet retired by poll
+    std::deque<uint64_t> pending;          // admitted, waiting for a slot
     uint64_t next_ticket = 1;
     bool shutting_down = false;
     std::mutex mu;
 };
 
 namespace {
+
+constexpr int64_t kMaxBatchPairs = (int64_t)1 << 24;
 
 // Device bytes a request needs: ASCII, packed queries, offsets, pairs, results.
 size_t request_bytes(int64_t n_res, int64_t n_q, int64_t n_cand)
@@ -130,16 +150,134 @@ size_t request_bytes(int64_t n_res, int64_t n_q, int64_t n_cand)
            align_up(8 * (size_t)n_cand) + align_up(sizeof(sw_result) * (size_t)n_cand);
 }
 
-// Completion of one request: results to the caller, memory and slot freed.
-int retire(sw_server* s, Request& r)
+// A finished launch: results to the callers, budget and slot freed.
+void complete(sw_server* s, Slot& sl, int status)
 {
-    hipError_t e = hipEventSynchronize(r.done);
-    if (e != hipSuccess) return SW_EDEVICE;
-    std::memcpy(r.out_host, r.staged, sizeof(sw_result) * (size_t)r.n_cand);
-    (void)hipEventDestroy(r.done);
-    s->arena.free(r.dev_off, r.dev_bytes);
-    s->slots[r.slot].busy = false;
-    return SW_OK;
+    Batch& b = sl.batch;
+    for (size_t k = 0; k < b.tickets.size(); ++k) {
+        Request& r = s->requests[b.tickets[k]];
+        if (status == SW_OK && r.n_cand)
+            std::memcpy(r.out_host, b.staged + b.first[k], sizeof(sw_result) * (size_t)r.n_cand);
+        r.status = status;
+        r.done = true;
+        s->reserved -= r.reserved;
+        std::vector<char>().swap(r.ascii);
+        std::vector<int64_t>().swap(r.offs);
+        std::vector<int32_t>().swap(r.cand);
+    }
+    if (b.done) (void)hipEventDestroy(b.done);
+    s->arena.free(b.dev_off, b.dev_bytes);
+    b = Batch();
+    sl.busy = false;
+}
+
+// Merge requests from the head of the queue into one launch on a free slot:
+// the queries are concatenated (query indexes of the candidates shifted
+// accordingly), copied in, packed and aligned against the resident set in
+// one call, and the results copied back.  Returns false when nothing could
+// be launched (no request waiting, or no arena space until a launch ends).
+bool launch(sw_server* s, Slot& sl)
+{
+    int64_t n_res = 0, n_q = 0, n_cand = 0;
+    size_t take = 0;
+    while (take < s->pending.size()) {
+        const Request& r = s->requests[s->pending[take]];
+        if (take > 0 && n_cand + r.n_cand > kMaxBatchPairs) break;
+        n_res += r.n_res;
+        n_q += r.n_q;
+        n_cand += r.n_cand;
+        ++take;
+    }
+    if (take == 0) return false;
+    const size_t need = request_bytes(n_res, n_q, n_cand);
+    const size_t off = s->arena.alloc(need);
+    if (off == SIZE_MAX) return false;
+
+    const size_t in_bytes = align_up((size_t)n_res) + align_up(8 * (size_t)(n_q + 1)) + align_up(8 * (size_t)n_cand);
+    const size_t stage = in_bytes + align_up(sizeof(sw_result) * (size_t)n_cand);
+    Batch b;
+    b.dev_off = off;
+    b.dev_bytes = need;
+    int status = SW_OK;
+    if (stage > sl.pinned_bytes) {
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+        sl.pinned = nullptr;
+        sl.pinned_bytes = 0;
+        const size_t bytes = std::max<size_t>(stage + stage / 4, 1 << 20);
+        if (hipHostMalloc((void**)&sl.pinned, bytes) != hipSuccess) status = SW_ENOMEM;
+        else sl.pinned_bytes = bytes;
+    }
+    // gather the requests into the staging buffer
+    char* h_ascii = sl.pinned;
+    int64_t* h_offs = reinterpret_cast<int64_t*>(sl.pinned + align_up((size_t)n_res));
+    int32_t* h_pairs = reinterpret_cast<int32_t*>(sl.pinned + align_up((size_t)n_res) + align_up(8 * (size_t)(n_q + 1)));
+    b.staged = reinterpret_cast<sw_result*>(sl.pinned + in_bytes);
+    int64_t res0 = 0, q0 = 0, c0 = 0;
+    for (size_t k = 0; k < take; ++k) {
+        const uint64_t t = s->pending.front();
+        s->pending.pop_front();
+        Request& r = s->requests[t];
+        b.tickets.push_back(t);
+        b.first.push_back(c0);
+        if (status != SW_OK) continue;
+        if (r.n_res) std::memcpy(h_ascii + res0, r.ascii.data(), (size_t)r.n_res);
+        for (int64_t i = 0; i < r.n_q; ++i) h_offs[q0 + i] = res0 + r.offs[i];
+        for (int64_t i = 0; i < r.n_cand; ++i) {
+            h_pairs[2 * (c0 + i)] = (int32_t)(q0 + r.cand[2 * i]);
+            h_pairs[2 * (c0 + i) + 1] = r.cand[2 * i + 1];
+        }
+        res0 += r.n_res;
+        q0 += r.n_q;
+        c0 += r.n_cand;
+    }
+    if (status == SW_OK) h_offs[n_q] = n_res;
+
+    char* d = s->arena.ptr(off);
+    char* d_ascii = d;
+    char* d_packed = d_ascii + align_up((size_t)n_res);
+    int64_t* d_offs = reinterpret_cast<int64_t*>(d_packed + align_up(sw_packed_bytes(n_res)));
+    int32_t* d_pairs = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_offs) + align_up(8 * (size_t)(n_q + 1)));
+    sw_result* d_out = reinterpret_cast<sw_result*>(reinterpret_cast<char*>(d_pairs) + align_up(8 * (size_t)n_cand));
+    hipStream_t st = sl.stream;
+    if (status == SW_OK && hipSetDevice(s->device) != hipSuccess) status = SW_EDEVICE;
+    if (status == SW_OK && n_res && hipMemcpyAsync(d_ascii, h_ascii, (size_t)n_res, hipMemcpyHostToDevice, st) != hipSuccess)
+        status = SW_EDEVICE;
+    if (status == SW_OK && hipMemcpyAsync(d_offs, h_offs, 8 * (size_t)(n_q + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+        status = SW_EDEVICE;
+    if (status == SW_OK && n_cand && hipMemcpyAsync(d_pairs, h_pairs, 8 * (size_t)n_cand, hipMemcpyHostToDevice, st) != hipSuccess)
+        status = SW_EDEVICE;
+    if (status == SW_OK) status = sw_pack(d_ascii, n_res, d_packed, sw_packed_bytes(n_res), st);
+    if (status == SW_OK && n_cand)
+        status = sw_align_sets(d_packed, d_offs, n_q, s->refs_packed, s->ref_offsets, s->n_refs, d_pairs, n_cand,
+                               &s->scoring, d_out, st, SW_NO_GRAPH);
+    if (status == SW_OK && n_cand &&
+        hipMemcpyAsync(b.staged, d_out, sizeof(sw_result) * (size_t)n_cand, hipMemcpyDeviceToHost, st) != hipSuccess)
+        status = SW_EDEVICE;
+    if (status == SW_OK && (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
+                            hipEventRecord(b.done, st) != hipSuccess))
+        status = SW_EDEVICE;
+    sl.batch = std::move(b);
+    sl.busy = true;
+    if (status != SW_OK) {
+        (void)hipStreamSynchronize(st);
+        complete(s, sl, status);
+    }
+    return true;
+}
+
+// Retire finished launches and start new ones while slots and requests allow.
+void pump(sw_server* s)
+{
+    for (auto& sl : s->slots) {
+        if (!sl.busy) continue;
+        const hipError_t e = hipEventQuery(sl.batch.done);
+        if (e == hipErrorNotReady) continue;
+        complete(s, sl, e == hipSuccess ? SW_OK : SW_EDEVICE);
+    }
+    for (auto& sl : s->slots) {
+        if (s->pending.empty()) break;
+        if (!sl.busy && !launch(s, sl)) break;
+    }
 }
 
 }  // namespace
@@ -186,93 +324,34 @@ SW_API int sw_server_submit(sw_server* s, const char* q_ascii, const int64_t* q_
 {
     if (!s || !q_offsets || n_q < 0 || n_cand < 0 || !ticket || (n_cand > 0 && (!cand || !out_host)))
         return SW_EINVAL;
+    if (n_cand > kMaxBatchPairs) return SW_ERANGE;
     const int64_t n_res = n_q > 0 ? q_offsets[n_q] : 0;
-    if (n_res < 0 || (n_res > 0 && !q_ascii)) return SW_EINVAL;
+    if (n_res < 0 || (n_res > 0 && !q_ascii) || q_offsets[0] != 0) return SW_EINVAL;
     for (int64_t k = 0; k < n_q; ++k)
-        if (q_offsets[k + 1] < q_offsets[k] || q_offsets[k] < 0) return SW_EINVAL;
+        if (q_offsets[k + 1] < q_offsets[k]) return SW_EINVAL;
+    for (int64_t k = 0; k < n_cand; ++k)
+        if (cand[2 * k] < 0 || cand[2 * k] >= n_q) return SW_ERANGE;
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->shutting_down) return SW_ECANCELED;
     const size_t need = request_bytes(n_res, n_q, n_cand);
     if (need > s->arena.size()) return SW_ENOMEM;  // can never be admitted
-    int slot = -1;
-    for (int k = 0; k < (int)s->slots.size(); ++k)
-        if (!s->slots[k].busy) {
-            slot = k;
-            break;
-        }
-    if (slot < 0) return SW_EAGAIN;
-    const size_t off = s->arena.alloc(need);
-    if (off == SIZE_MAX) return SW_EAGAIN;
-    Slot& sl = s->slots[slot];
-    if (hipSetDevice(s->device) != hipSuccess) {
-        s->arena.free(off, need);
-        return SW_EDEVICE;
-    }
-    // pinned staging: inputs then results
-    const size_t in_bytes = align_up((size_t)n_res) + align_up(8 * (size_t)(n_q + 1)) + align_up(8 * (size_t)n_cand);
-    const size_t stage = in_bytes + align_up(sizeof(sw_result) * (size_t)n_cand);
-    if (stage > sl.pinned_bytes) {
-        if (sl.pinned) (void)hipHostFree(sl.pinned);
-        sl.pinned = nullptr;
-        sl.pinned_bytes = 0;
-        if (hipHostMalloc((void**)&sl.pinned, std::max<size_t>(stage, 1 << 20)) != hipSuccess) {
-            s->arena.free(off, need);
-            return SW_ENOMEM;
-        }
-        sl.pinned_bytes = std::max<size_t>(stage, 1 << 20);
-    }
-    char* p = sl.pinned;
-    char* h_ascii = p;
-    int64_t* h_offs = reinterpret_cast<int64_t*>(p + align_up((size_t)n_res));
-    int32_t* h_pairs = reinterpret_cast<int32_t*>(p + align_up((size_t)n_res) + align_up(8 * (size_t)(n_q + 1)));
-    sw_result* h_out = reinterpret_cast<sw_result*>(p + in_bytes);
-    if (n_res) std::memcpy(h_ascii, q_ascii, (size_t)n_res);
-    std::memcpy(h_offs, q_offsets, 8 * (size_t)(n_q + 1));
-    if (n_cand) std::memcpy(h_pairs, cand, 8 * (size_t)n_cand);
-
-    char* d = s->arena.ptr(off);
-    char* d_ascii = d;
-    char* d_packed = d_ascii + align_up((size_t)n_res);
-    int64_t* d_offs = reinterpret_cast<int64_t*>(d_packed + align_up(sw_packed_bytes(n_res)));
-    int32_t* d_pairs = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_offs) + align_up(8 * (size_t)(n_q + 1)));
-    sw_result* d_out = reinterpret_cast<sw_result*>(reinterpret_cast<char*>(d_pairs) + align_up(8 * (size_t)n_cand));
-
-    hipStream_t st = sl.stream;
-    int rc = SW_OK;
-    auto fail = [&](int code) {
-        (void)hipStreamSynchronize(st);
-        s->arena.free(off, need);
-        return code;
-    };
-    if (n_res && hipMemcpyAsync(d_ascii, h_ascii, (size_t)n_res, hipMemcpyHostToDevice, st) != hipSuccess)
-        return fail(SW_EDEVICE);
-    if (hipMemcpyAsync(d_offs, h_offs, 8 * (size_t)(n_q + 1), hipMemcpyHostToDevice, st) != hipSuccess)
-        return fail(SW_EDEVICE);
-    if (n_cand && hipMemcpyAsync(d_pairs, h_pairs, 8 * (size_t)n_cand, hipMemcpyHostToDevice, st) != hipSuccess)
-        return fail(SW_EDEVICE);
-    if ((rc = sw_pack(d_ascii, n_res, d_packed, sw_packed_bytes(n_res), st)) != SW_OK) return fail(rc);
-    if (n_cand) {
-        rc = sw_align_sets(d_packed, d_offs, n_q, s->refs_packed, s->ref_offsets, s->n_refs, d_pairs, n_cand,
-                           &s->scoring, d_out, st, SW_NO_GRAPH);
-        if (rc != SW_OK) return fail(rc);
-        if (hipMemcpyAsync(h_out, d_out, sizeof(sw_result) * (size_t)n_cand, hipMemcpyDeviceToHost, st) !=
-            hipSuccess)
-            return fail(SW_EDEVICE);
-    }
+    pump(s);
+    if (s->reserved + need > s->arena.size()) return SW_EAGAIN;
     Request r;
-    r.ticket = s->next_ticket++;
-    r.slot = slot;
-    r.dev_off = off;
-    r.dev_bytes = need;
+    r.n_q = n_q;
+    r.n_res = n_res;
     r.n_cand = n_cand;
+    r.reserved = need;
     r.out_host = out_host;
-    r.staged = h_out;
-    if (hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(r.done, st) != hipSuccess)
-        return fail(SW_EDEVICE);
-    sl.busy = true;
-    s->inflight[r.ticket] = r;
-    *ticket = r.ticket;
+    r.ascii.assign(q_ascii, q_ascii + n_res);
+    r.offs.assign(q_offsets, q_offsets + n_q + 1);
+    r.cand.assign(cand, cand + 2 * n_cand);
+    const uint64_t t = s->next_ticket++;
+    s->requests.emplace(t, std::move(r));
+    s->reserved += need;
+    s->pending.push_back(t);
+    pump(s);
+    *ticket = t;
     return SW_OK;
 }
 
@@ -280,13 +359,12 @@ SW_API int sw_server_poll(sw_server* s, uint64_t ticket)
 {
     if (!s) return SW_EINVAL;
     std::lock_guard<std::mutex> lock(s->mu);
-    auto it = s->inflight.find(ticket);
-    if (it == s->inflight.end()) return SW_EINVAL;
-    hipError_t e = hipEventQuery(it->second.done);
-    if (e == hipErrorNotReady) return SW_EAGAIN;
-    if (e != hipSuccess) return SW_EDEVICE;
-    int rc = retire(s, it->second);
-    s->inflight.erase(it);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return SW_EINVAL;
+    if (!it->second.done) pump(s);
+    if (!it->second.done) return SW_EAGAIN;
+    const int rc = it->second.status;
+    s->requests.erase(it);
     return rc;
 }
 
@@ -310,8 +388,11 @@ SW_API int sw_server_stats(sw_server* s, int64_t* inflight, int64_t* bytes_in_us
 {
     if (!s) return SW_EINVAL;
     std::lock_guard<std::mutex> lock(s->mu);
-    if (inflight) *inflight = (int64_t)s->inflight.size();
-    if (bytes_in_use) *bytes_in_use = (int64_t)s->arena.used();
+    pump(s);
+    int64_t n = 0;
+    for (const auto& kv : s->requests) n += kv.second.done ? 0 : 1;
+    if (inflight) *inflight = n;
+    if (bytes_in_use) *bytes_in_use = (int64_t)s->reserved;
     if (budget) *budget = (int64_t)s->arena.size();
     return SW_OK;
 }
@@ -328,16 +409,17 @@ SW_API int sw_server_destroy(sw_server* s)
     {
         std::lock_guard<std::mutex> lock(s->mu);
         s->shutting_down = true;
-        for (auto& kv : s->inflight) {
-            (void)hipEventSynchronize(kv.second.done);
-            (void)hipEventDestroy(kv.second.done);
-        }
-        s->inflight.clear();
         for (auto& sl : s->slots) {
+            if (sl.busy) {
+                (void)hipEventSynchronize(sl.batch.done);
+                complete(s, sl, SW_ECANCELED);
+            }
             (void)hipStreamSynchronize(sl.stream);
             (void)hipStreamDestroy(sl.stream);
             if (sl.pinned) (void)hipHostFree(sl.pinned);
         }
+        s->requests.clear();
+        s->pending.clear();
         s->arena.release();
     }
     delete s;

@@ -87,8 +87,14 @@ def test_admission_limits(setup):
         tiny.close()
     one = Server(refs.packed, refs.offsets, hbm_budget=1 << 30, max_slots=1)
     try:
+        exp = oracle_for(w, q, qo, cand)
         t = one.submit(q, qo, cand)
-        assert one.submit(q, qo, cand) is None           # single slot busy
-        one.wait(t)
+        # the slot is busy: these queue and run merged into one later launch
+        more = [one.submit(*b) for b in w.batches[:5]]
+        assert all(x is not None for x in more)
+        assert (one.wait(t) == exp).all()
+        for x, b in zip(more, w.batches[:5]):
+            assert (one.wait(x) == oracle_for(w, *b)).all()
+        assert one.stats()["inflight"] == 0
     finally:
         one.close()
