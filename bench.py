@@ -21,8 +21,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# int32 VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# VALU peaks of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz instructions per
+# second; a packed 16-bit instruction does the work of two cells
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_PACKED16_TOPS = 2 * PEAK_INT32_TOPS
 ALGO_OPS_PER_CELL = 8  # sub, 2x(sub,max) for E and F, add, max3, running max
 
 
@@ -191,7 +193,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "u16x2+i32",
         "data": "synthetic",
         "config": {"workload": "1m-lognormal280", "pairs": ps.n_pairs, "sequences": ps.n_seqs,
                    "cells": cells, "scoring": "BLOSUM62 gap_open 11 gap_extend 1",
@@ -204,11 +206,14 @@ def main():
         "plain": plain,
         "persistent_over_plain": round(gcups / plain["gcups"], 3) if plain else None,
         "parity_sample": "%d/%d bit-exact vs CPU oracle" % (n_ok, len(sample)),
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
-                     "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_PACKED16_TOPS, 2),
+                     "unit": "TOP/s", "frac": round(achieved / PEAK_PACKED16_TOPS, 4),
                      "traffic": stored_traffic(R, ps.n_pairs),
-                     "kernel": "k_persistent<%d>, %d int32 ops per cell x %d cells per launch" % (
-                         R, ALGO_OPS_PER_CELL, cells)},
+                     "kernel": "k_persistent<%d>, %d ops per cell x %d cells per launch" % (
+                         R, ALGO_OPS_PER_CELL, cells),
+                     "peak_basis": "packed 16-bit VALU (2 cells per instruction), the arithmetic of the "
+                                   "score passes; int32 peak %.2f TOP/s gives frac %.4f" % (
+                                       PEAK_INT32_TOPS, achieved / PEAK_INT32_TOPS)},
         "paper_context": "paper: 690.6 M alignments/s and 176.3 TCUPS peak on 20,184 V100 GPUs "
                          "(whole application, multi-node; not a 1-GPU target)",
     }

@@ -87,21 +87,23 @@ SW_API size_t sw_packed_bytes(int64_t n_residues);
 /*
  * Encode a concatenated ASCII buffer of n_residues residues (device memory)
  * into the library's packed 5-bit form: a 4-bit plane (8 residues per 32-bit
- * word) plus a 1-bit plane (32 residues per word), see DESIGN notes in the
- * source.  Residue positions are unchanged, so the same int64 offsets index
- * sequences in the ASCII and in the packed buffer.  packed_cap must be at
- * least sw_packed_bytes(n_residues).  Letters outside the alphabet are stored
- * as a padding symbol that never aligns; they are reported as SW_ECODE by the
- * next sw_check on this device or by sw_batch_align with SW_VALIDATE.
- * Errors: SW_EINVAL (null pointer, n_residues < 0), SW_ENOMEM (packed_cap too
- * small), SW_EDEVICE.
+ * word) followed by a 1-bit plane (32 residues per word), the layout being
+ * described in the library source.  Residue positions are unchanged, so the
+ * same int64 offsets index sequences in the ASCII and in the packed buffer.
+ * packed_dev must be 16-byte aligned and packed_cap at least
+ * sw_packed_bytes(n_residues).  Letters outside the alphabet are stored as a
+ * padding symbol that scores -4 (the lowest BLOSUM62 score) against every
+ * residue; they are reported as SW_ECODE by the next sw_check on this device
+ * or by sw_batch_align with SW_VALIDATE, and the results of pairs holding
+ * them are not defined.  Errors: SW_EINVAL (null or misaligned pointer,
+ * n_residues < 0), SW_ENOMEM (packed_cap too small), SW_EDEVICE.
  */
 SW_API int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, size_t packed_cap,
             void* stream);
 
 /*
  * Align n_pairs candidate pairs.
- *   packed_dev    buffer written by sw_pack
+ *   packed_dev    buffer written by sw_pack (16-byte aligned)
  *   offsets_dev   int64[n_seqs + 1]: sequence k is residues offsets[k] ..
  *                 offsets[k+1]-1 of the packed buffer (non-decreasing)
  *   pairs_dev     int32[2 * n_pairs]: (query index, reference index) per pair

@@ -371,6 +371,7 @@ size_t sw_packed_bytes(int64_t n_residues)
 int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, size_t packed_cap, void* stream)
 {
     if (!packed_dev || n_residues < 0 || (n_residues > 0 && !ascii_dev)) return SW_EINVAL;
+    if (reinterpret_cast<uintptr_t>(packed_dev) & 15u) return SW_EINVAL;
     if (packed_cap < packed_bytes(n_residues)) return SW_ENOMEM;
     std::lock_guard<std::mutex> lock(g_mutex);
     Device* d = nullptr;
@@ -391,6 +392,8 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
         return SW_EINVAL;
     if (n_pairs == 0) return SW_OK;
     if (!q_packed_dev || !q_offsets_dev || !r_packed_dev || !r_offsets_dev || !pairs_dev || !out_dev)
+        return SW_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(q_packed_dev) | reinterpret_cast<uintptr_t>(r_packed_dev)) & 15u)
         return SW_EINVAL;
     if (n_pairs > (int64_t)0x7FFFFFFF - 64 || n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF)
         return SW_ERANGE;

@@ -119,45 +119,36 @@ void matrix_ncbi(int8_t out[kNumSym * kNumSym], char letters[kNumSym + 1])
 const char* code_order() { return kCodeOrder; }
 
 // ------------------------------------------------------------------ packed residues
-// Word of the nibble / high plane holding residue p (p may be as low as
-// -kGuardRes).  Planes are interleaved in 256-residue blocks of 40 words.
-__device__ __forceinline__ int64_t nib_word(int64_t p)
-{
-    int64_t q = p + kGuardRes;
-    return (q >> 8) * 40 + ((q >> 3) & 31);
-}
-__device__ __forceinline__ int64_t hib_word(int64_t p)
-{
-    int64_t q = p + kGuardRes;
-    return (q >> 8) * 40 + 32 + ((q >> 5) & 7);
-}
-
 // A sequence view: residues B + x for x >= -256 addressed with 32-bit offsets
-// from the block before the one holding B.
+// from the 256-residue block before the one holding B, in both planes.
 struct SeqView {
-    const uint32_t* ptr;
+    const uint32_t* nib;
+    const uint32_t* hib;
     int off;
 };
 
-__device__ __forceinline__ SeqView seq_view(const uint32_t* __restrict__ blk, int64_t B)
+__device__ __forceinline__ const uint32_t* high_plane(const uint32_t* nib_plane, const PackedHeader* h)
+{
+    return nib_plane + h->n_blocks * 32;
+}
+
+__device__ __forceinline__ SeqView seq_view(const uint32_t* __restrict__ nib_plane, const PackedHeader* h, int64_t B)
 {
     const int64_t q = B + kGuardRes;
     SeqView v;
-    v.ptr = blk + ((q >> 8) - 1) * 40;
+    v.nib = nib_plane + ((q >> 8) - 1) * 32;
+    v.hib = high_plane(nib_plane, h) + ((q >> 8) - 1) * 8;
     v.off = (int)(q & 255) + 256;
     return v;
 }
-
-__device__ __forceinline__ int view_nib(int q) { return (q >> 8) * 40 + ((q >> 3) & 31); }
-__device__ __forceinline__ int view_hib(int q) { return (q >> 8) * 40 + 32 + ((q >> 5) & 7); }
 
 // Codes of the 8 residues B+x .. B+x+7: nibble k of nw, bit k of hw.
 __device__ __forceinline__ void window8(const SeqView& v, int x, uint32_t& nw, uint32_t& hw)
 {
     const int q = v.off + x;
-    const uint32_t a0 = v.ptr[view_nib(q)], a1 = v.ptr[view_nib(q + 8)];
+    const uint32_t a0 = v.nib[q >> 3], a1 = v.nib[(q >> 3) + 1];
     nw = __builtin_amdgcn_alignbit(a1, a0, (uint32_t)(q & 7) * 4u);
-    const uint32_t b0 = v.ptr[view_hib(q)], b1 = v.ptr[view_hib(q + 32)];
+    const uint32_t b0 = v.hib[q >> 5], b1 = v.hib[(q >> 5) + 1];
     hw = __builtin_amdgcn_alignbit(b1, b0, (uint32_t)(q & 31));
 }
 
@@ -165,7 +156,7 @@ __device__ __forceinline__ void window8(const SeqView& v, int x, uint32_t& nw, u
 __device__ __forceinline__ uint32_t code_at(const SeqView& v, int x)
 {
     const int q = v.off + x;
-    return ((v.ptr[view_nib(q)] >> ((q & 7) * 4)) & 15u) | (((v.ptr[view_hib(q)] >> (q & 31)) & 1u) << 4);
+    return ((v.nib[q >> 3] >> ((q & 7) * 4)) & 15u) | (((v.hib[q >> 5] >> (q & 31)) & 1u) << 4);
 }
 
 // Codes of R consecutive rows starting at `row0`, read forwards from the view
@@ -404,8 +395,8 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
     const int wss = uni(wave_max(my_ss));
     const int wc = uni(wave_max(my_ss > 0 ? my_chunks : 0));
     bool done = my_ss == 0 || (REV && target <= 0 && !ONE);
-    const SeqView qv = seq_view(a.qblk, Q0);
-    const SeqView rv = seq_view(a.rblk, R0);
+    const SeqView qv = seq_view(a.qblk, a.qhdr, Q0);
+    const SeqView rv = seq_view(a.rblk, a.rhdr, R0);
     uint4* slot4 = reinterpret_cast<uint4*>(slot + (ONE ? (int64_t)min(max(one_buf, 0), 2) * boundary_buf_words(P) : 0)) +
                    SW * g;
     uint4* x_mine = xbuf + SW * lane;
@@ -637,8 +628,8 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
     const int wss = uni(wave_max(my_ss));
     const int wc = uni(wave_max(my_ss > 0 ? my_chunks : 0));
     bool done = my_ss == 0 || (REV && target <= 0);
-    const SeqView qv = seq_view(a.qblk, Q0);
-    const SeqView rv = seq_view(a.rblk, R0);
+    const SeqView qv = seq_view(a.qblk, a.qhdr, Q0);
+    const SeqView rv = seq_view(a.rblk, a.rhdr, R0);
     uint32_t* grp_slot = slot + 8 * g;  // [buffer][chunk][group][8 cells]
     // hand-over between lanes: 8 words per lane at the end of an iteration
     // (7 used) and one word in the middle
@@ -672,7 +663,50 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
 #pragma unroll
         for (int k = 0; k < 8; ++k) botp[k] = 0;
         uint4 tn0 = make_uint4(0, 0, 0, 0), tn1 = make_uint4(0, 0, 0, 0);
-        uint32_t nw_n, hw_n;
+        uint32_t nw_n = 0, hw_n = 0;
+        // One lane per pair: the reference comes through LDS.  Every 8 chunks
+        // a lane loads the aligned 16-byte groups holding the next 72
+        // residues (3 of the nibble plane, 2 of the high plane) one batch
+        // ahead and writes them to its column of the staging area ([word]
+        // [lane], conflict-free for any per-lane offset); each chunk reads
+        // its two words per plane from there.  Per-chunk global loads of
+        // scattered words missed the L1 most of the time.
+        uint4 sn0, sn1, sn2, sh0, sh1;  // staged batch
+        const int s0 = rv.off + (REV ? -7 : 0);
+        const int last_batch = max(my_chunks - 1, 0) >> 3;
+        auto batch_lo = [&](int bb) __attribute__((always_inline)) -> int {
+            const int b = min(bb, last_batch);  // lanes past their end re-read their last batch
+            return REV ? s0 - 64 * b - 56 : s0 + 64 * b;
+        };
+        auto load_batch = [&](int bb) __attribute__((always_inline)) {
+            const int lo = batch_lo(bb);
+            const uint4* np = reinterpret_cast<const uint4*>(rv.nib + ((lo >> 3) & ~3));
+            const uint4* hp = reinterpret_cast<const uint4*>(rv.hib + ((lo >> 5) & ~3));
+            sn0 = np[0];
+            sn1 = np[1];
+            sn2 = np[2];
+            sh0 = hp[0];
+            sh1 = hp[1];
+        };
+        auto store_batch = [&]() __attribute__((always_inline)) {
+            const uint32_t v[20] = {sn0.x, sn0.y, sn0.z, sn0.w, sn1.x, sn1.y, sn1.z, sn1.w, sn2.x, sn2.y,
+                                    sn2.z, sn2.w, sh0.x, sh0.y, sh0.z, sh0.w, sh1.x, sh1.y, sh1.z, sh1.w};
+#pragma unroll
+            for (int w = 0; w < 20; ++w) xw[w * kWave + lane] = v[w];
+        };
+        // window of chunk c from the staged batch c / 8
+        auto window_lds = [&](int c) __attribute__((always_inline)) {
+            const int b = c >> 3, j = c & 7;
+            const int lo = batch_lo(b);
+            const int st = REV ? lo + 56 - 8 * j : lo + 8 * j;  // first residue of the window
+            // inside the staged words (lanes past their end re-read their last batch)
+            const int wn = min((st >> 3) - ((lo >> 3) & ~3), 10);
+            const int wh = min((st >> 5) - ((lo >> 5) & ~3), 6);
+            const uint32_t n0 = xw[wn * kWave + lane], n1 = xw[(wn + 1) * kWave + lane];
+            const uint32_t h0 = xw[(12 + wh) * kWave + lane], h1 = xw[(13 + wh) * kWave + lane];
+            nw_n = __builtin_amdgcn_alignbit(n1, n0, (uint32_t)(st & 7) * 4u);
+            hw_n = __builtin_amdgcn_alignbit(h1, h0, (uint32_t)(st & 31));
+        };
         auto fetch = [&](int cn) __attribute__((always_inline)) {
             // load from an index inside the pair's chunks, then select: the
             // address is always valid and no select of addresses arises
@@ -681,8 +715,14 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             const uint4 v0 = in4[cc * (G * 2)], v1 = in4[cc * (G * 2) + 1];
             tn0 = real ? v0 : make_uint4(0, 0, 0, 0);
             tn1 = real ? v1 : make_uint4(0, 0, 0, 0);
-            window8(rv, chunk_x(cn), nw_n, hw_n);
+            if constexpr (P > 1) window8(rv, chunk_x(cn), nw_n, hw_n);
         };
+        if constexpr (P == 1) {
+            load_batch(0);
+            store_batch();
+            load_batch(1);
+            window_lds(0);
+        }
         fetch(-u);
         // Iteration t: lane u on chunk c = t - u, A on columns 8c .. 8c+7,
         // B on 8c-1 .. 8c+6.  Each lane needs my_chunks + 1 chunk iterations
@@ -708,6 +748,16 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 top[6] = up ? e1.z : top[6];
             }
             uint32_t nw = nw_n, hw = hw_n;
+            if constexpr (P == 1) {
+                // c == t here.  The next chunk's window is read now (from the
+                // next batch when one starts there: staged data to LDS first,
+                // the batch after it in flight).
+                if ((c & 7) == 7) {
+                    store_batch();
+                    load_batch((c >> 3) + 2);
+                }
+                window_lds(c + 1);
+            }
             if (t + 1 <= wc + P - 1) fetch(c + 1);
             uint32_t bq[8];
 #pragma unroll
@@ -1017,10 +1067,9 @@ __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, uint32_t* _
             }
         }
     }
-    const int64_t blkidx = t >> 3, sub = t & 7;  // 8 high words (256 residues) per block
-    uint32_t* b = blk + blkidx * 40;
-    for (int k = 0; k < 4; ++k) b[4 * sub + k] = nib[k];
-    b[32 + sub] = hib;
+    // nibble plane words 4t .. 4t+3, high plane word t (after n_hib_words * 4 nibble words)
+    *reinterpret_cast<uint4*>(blk + 4 * t) = make_uint4(nib[0], nib[1], nib[2], nib[3]);
+    blk[4 * n_hib_words + t] = hib;
     if (bad) atomicOr((unsigned*)err, (unsigned)kErrCode);
 }
 
@@ -1180,7 +1229,7 @@ __global__ void k_pack_header(PackedHeader* h, int64_t n)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         h->magic = kPackMagic;
-        h->version = 1;
+        h->version = 2;  // planar: nibble plane, then high plane
         h->n_residues = n;
         h->n_blocks = (kGuardRes + n + kTailRes + 255) / 256 + 1;
         h->total_bytes = kHeaderBytes + h->n_blocks * 160;

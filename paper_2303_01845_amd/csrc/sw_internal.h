@@ -11,21 +11,23 @@
 namespace swk {
 
 // ---------------------------------------------------------------- packed format
-// A packed buffer is a 256-byte header followed by 160-byte blocks.  Block b
-// holds residue positions [256 b - kGuardRes, 256 (b+1) - kGuardRes):
-//   words 0..31: nibble plane, residue at block offset o -> bits 4*(o&7).. of word o>>3
-//   words 32..39: high plane,  residue at block offset o -> bit o&31 of word 32 + (o>>5)
-// code = nibble | high << 4, in the library's own symbol order.  The guard of
-// kGuardRes residues before position 0 and the slack after the last residue
-// keep every 8-, 16- and 32-residue window that overlaps a sequence inside
-// the buffer.  Nothing in the layout depends on the number of residues, so
-// the aligner needs only the buffer pointer.
+// A packed buffer is a 256-byte header followed by two planes over residue
+// positions p in [-kGuardRes, 256 n_blocks - kGuardRes):
+//   nibble plane (32 n_blocks words): residue q = p + kGuardRes in bits
+//     4*(q&7).. of word q>>3
+//   high plane (8 n_blocks words, right after): bit q&31 of word q>>5
+// code = nibble | high << 4, in the library's own symbol order.  Each plane is
+// contiguous, so a run of residues is a run of words: a lane can fetch 32
+// residues with one 16-byte load.  The guard of kGuardRes residues before
+// position 0 and the slack after the last residue keep every window of a few
+// dozen residues that overlaps a sequence inside the buffer.  The aligner
+// finds the high plane from n_blocks in the header.
 constexpr uint32_t kPackMagic = 0x35575350u;  // "PSW5"
 constexpr int kGuardRes = 64;
-constexpr int kTailRes = 192;
+constexpr int kTailRes = 512;
 constexpr int kHeaderBytes = 256;
 constexpr int kNumSym = 24;
-constexpr int kPadCode = 24;  // beyond a sequence end; scores -128 against everything
+constexpr int kPadCode = 24;  // beyond a sequence end (and invalid letters); scores -4 against everything
 constexpr int kNumCodes = 25;
 
 struct PackedHeader {
@@ -47,7 +49,7 @@ constexpr int kMaxInterLen = 1024;
 constexpr int kMaxP16Len = 4096;      // longest pair a 16-lane group may get; the packed
                                       // 16-bit pass also covers whole waves up to this
 constexpr int kDefaultGroup16Max = 2048;  // default group16_max_len
-constexpr int kXbufBytes = 64 * 64;   // LDS exchange buffer: 16 words per lane
+constexpr int kXbufBytes = 64 * 96;   // LDS exchange / staging buffer: 24 words per lane
 constexpr int kWideCostBins = 512;     // floor(16 * log2(m*n)) for long (wide) pairs
 constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
 constexpr int kInterCells = kMaxInterStrips * kMaxInterChunks;
