@@ -178,8 +178,9 @@ def main():
                  "ms_per_step": round(pwall / plain_steps * 1e3, 3), "align_ms": round(palign_ms, 3),
                  "kernel_ms": round(pkernel_ms, 3), "steps": plain_steps}
 
-    # dominant kernel: the persistent alignment kernel, timed by HIP events
-    # recorded by the library on the launch stream around that launch alone
+    # dominant kernel: the persistent alignment kernel, launched twice per
+    # step (forward passes, then start passes), each launch timed by HIP
+    # events that the library records on the launch stream around it
     achieved = ALGO_OPS_PER_CELL * cells / (kernel_ms * 1e-3) / 1e12
     R = tuning["rows_per_lane"]
     res = {
@@ -209,8 +210,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_PACKED16_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved / PEAK_PACKED16_TOPS, 4),
                      "traffic": stored_traffic(R, ps.n_pairs),
-                     "kernel": "k_persistent<%d>, %d ops per cell x %d cells per launch" % (
-                         R, ALGO_OPS_PER_CELL, cells),
+                     "kernel": "k_persistent<%d>, %d ops per cell x %d cells per step; two launches per "
+                               "step (forward, start), mean launch %.3f ms" % (
+                                   R, ALGO_OPS_PER_CELL, cells, kernel_ms / 2),
                      "peak_basis": "packed 16-bit VALU (2 cells per instruction), the arithmetic of the "
                                    "score passes; int32 peak %.2f TOP/s gives frac %.4f" % (
                                        PEAK_INT32_TOPS, achieved / PEAK_INT32_TOPS)},

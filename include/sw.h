@@ -72,7 +72,7 @@ typedef struct {
 } sw_scoring;
 
 /* flags of sw_batch_align */
-#define SW_PERSISTENT 0u /* default: one persistent launch over a device work queue, replayed as a HIP graph */
+#define SW_PERSISTENT 0u /* default: persistent launches over a device work queue, replayed as HIP graphs */
 #define SW_PLAIN 1u      /* one launch per length bucket, static work split, no queue, no graph */
 #define SW_VALIDATE 2u   /* synchronise before returning and report SW_ERANGE / SW_ECODE found on the device */
 #define SW_NO_GRAPH 4u   /* persistent form without HIP-graph capture */
@@ -111,6 +111,9 @@ SW_API int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, 
  *   out_dev       sw_result[n_pairs], written in pair order
  *   flags         SW_PERSISTENT (0) | SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH |
  *                 SW_TIMED
+ * The persistent form runs every forward pass first and then the start
+ * passes, regrouped by the size of their regions; the plain form runs both
+ * passes of a pair together.
  * A pair with an index outside [0, n_seqs) or a sequence longer than
  * SW_MAX_SEQ_LEN gets score -1 and coordinates -1 and raises SW_ERANGE on the
  * next check; an empty sequence gives score 0.  n_pairs == 0 does nothing.
@@ -144,13 +147,14 @@ SW_API int sw_check(void* stream);
 
 /*
  * Device time of the alignment kernels of the calls made with SW_TIMED on
- * `stream` since the previous read: the persistent kernel of each persistent
- * call (the sorting kernels before it are not included; with graph replay the
- * two parts are separate graphs with the events between them), or the
- * per-bucket launch series of each SW_PLAIN call.  Synchronises `stream`,
- * writes the summed milliseconds to *kernel_ms and the number of calls to
- * *calls, and forgets them.  At most 4096 timed calls may be outstanding on a
- * stream; a further SW_TIMED call returns SW_ENOMEM before launching anything.
+ * `stream` since the previous read: the two persistent launches of each
+ * persistent call (forward passes, then start passes; the sorting kernels
+ * before each are not included -- with graph replay every part is its own
+ * graph, with the events between them), or the per-bucket launch series of
+ * each SW_PLAIN call.  Synchronises `stream`, writes the summed milliseconds
+ * to *kernel_ms and the number of calls to *calls, and forgets them.  At most
+ * 4096 timed calls may be outstanding on a stream; a further SW_TIMED call
+ * returns SW_ENOMEM before launching anything.
  * Errors: SW_EINVAL (null output pointer), SW_EDEVICE.
  */
 SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);

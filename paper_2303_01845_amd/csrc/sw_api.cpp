@@ -148,21 +148,28 @@ struct Workspace {
     int64_t scratch_words = 0;
     uint32_t* scratch = nullptr;
     int32_t* host_rank_start = nullptr;  // pinned, plain form only
-    // persistent form: the sorting kernels and the persistent kernel are two
-    // graphs so that timing events can sit between them
+    // persistent form: sort for the forward pass, forward pass, sort for the
+    // start pass, start pass -- four graphs so that timing events can sit
+    // around the two persistent launches
     struct Graphs {
-        hipGraphExec_t prepare = nullptr, align = nullptr;
+        hipGraphExec_t g[4] = {nullptr, nullptr, nullptr, nullptr};
+        void destroy()
+        {
+            for (auto& x : g) {
+                if (x) (void)hipGraphExecDestroy(x);
+                x = nullptr;
+            }
+        }
     };
     std::map<GraphKey, Graphs> graphs;
-    // SW_TIMED: event pairs recorded and not yet read, and a pool to reuse
+    // SW_TIMED: event pairs recorded and not yet read (one per persistent
+    // launch), the number of calls they belong to, and a pool to reuse
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, event_pool;
+    int64_t timed_calls = 0;
 
     void drop_graphs()
     {
-        for (auto& g : graphs) {
-            (void)hipGraphExecDestroy(g.second.prepare);
-            (void)hipGraphExecDestroy(g.second.align);
-        }
+        for (auto& g : graphs) g.second.destroy();
         graphs.clear();
     }
 
@@ -324,7 +331,7 @@ int capture(Device& d, F launch, hipGraphExec_t* out)
     return SW_OK;
 }
 
-constexpr size_t kMaxTimed = 4096;
+constexpr size_t kMaxTimed = 8192;
 
 // Event pair for one SW_TIMED call (from the pool, else new).
 int timing_events(Workspace& w, std::pair<hipEvent_t, hipEvent_t>* ev)
@@ -439,33 +446,49 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     a.group16_max_len = d.group16_max;
 
     const bool timed = flags & SW_TIMED;
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    std::pair<hipEvent_t, hipEvent_t> ev[2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     if (timed) {
-        if (w.timed.size() >= kMaxTimed) return SW_ENOMEM;
-        if ((rc = timing_events(w, &ev))) return rc;
-        w.event_pool.push_back(ev);  // back in the pool until recorded
-    }
-    auto begin_timed = [&]() -> hipError_t {
-        return timed ? hipEventRecord(ev.first, stream) : hipSuccess;
-    };
-    auto end_timed = [&]() -> hipError_t {
-        if (!timed) return hipSuccess;
-        hipError_t e = hipEventRecord(ev.second, stream);
-        if (e == hipSuccess) {
-            w.event_pool.pop_back();
-            w.timed.push_back(ev);
+        if (w.timed.size() + 2 > kMaxTimed) return SW_ENOMEM;
+        if ((rc = timing_events(w, &ev[0]))) return rc;
+        if ((rc = timing_events(w, &ev[1]))) {
+            w.event_pool.push_back(ev[0]);
+            return rc;
         }
+        // both back in the pool until recorded (taken out again by finish_timed)
+        w.event_pool.push_back(ev[0]);
+        w.event_pool.push_back(ev[1]);
+    }
+    int n_timed = 0;
+    auto begin_timed = [&](int k) -> hipError_t {
+        return timed ? hipEventRecord(ev[k].first, stream) : hipSuccess;
+    };
+    auto end_timed = [&](int k) -> hipError_t {
+        if (!timed) return hipSuccess;
+        hipError_t e = hipEventRecord(ev[k].second, stream);
+        if (e == hipSuccess) ++n_timed;
         return e;
+    };
+    // move the recorded pairs from the pool to the timed list
+    auto finish_timed = [&]() {
+        if (!timed) return;
+        for (int k = 0; k < 2; ++k) {
+            auto it = std::find(w.event_pool.begin(), w.event_pool.end(), ev[k]);
+            if (it != w.event_pool.end()) w.event_pool.erase(it);
+            if (k < n_timed) w.timed.push_back(ev[k]);
+            else w.event_pool.push_back(ev[k]);
+        }
+        if (n_timed > 0) ++w.timed_calls;
     };
 
     if (flags & SW_PLAIN) {
         a.rank_cell = d.rank_cell_plain;
+        a.phase = 0;
         HIP_TRY(launch_prepare(a, stream), "prepare launch");
         HIP_TRY(hipMemcpyAsync(w.host_rank_start, w.rank_start, sizeof(int32_t) * (kNumCells + 1),
                                hipMemcpyDeviceToHost, stream),
                 "bucket sizes");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-        HIP_TRY(begin_timed(), "hipEventRecord");
+        HIP_TRY(begin_timed(0), "hipEventRecord");
         for (const auto& b : d.ord.buckets) {
             const int first = w.host_rank_start[b.rank_begin];
             const int count = w.host_rank_start[b.rank_end] - first;
@@ -474,39 +497,55 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             const int items = (count + per_item - 1) / per_item;
             HIP_TRY(launch_plain(a, b.kind, first, count, std::min(items, grid), stream), "plain launch");
         }
-        HIP_TRY(end_timed(), "hipEventRecord");
+        HIP_TRY(end_timed(0), "hipEventRecord");
+        finish_timed();
     } else {
+        // forward pass for every pair, then the start passes regrouped by the
+        // size of their region (lanes of an item finish together)
         a.rank_cell = d.rank_cell_persistent;
+        Args a1 = a, a2 = a;
+        a1.phase = 1;
+        a2.phase = 2;
         if (flags & SW_NO_GRAPH) {
-            HIP_TRY(launch_prepare(a, stream), "prepare launch");
-            HIP_TRY(begin_timed(), "hipEventRecord");
-            HIP_TRY(launch_persistent(a, grid, stream), "persistent launch");
-            HIP_TRY(end_timed(), "hipEventRecord");
+            HIP_TRY(launch_prepare(a1, stream), "prepare launch");
+            HIP_TRY(begin_timed(0), "hipEventRecord");
+            HIP_TRY(launch_persistent(a1, grid, stream), "persistent launch");
+            HIP_TRY(end_timed(0), "hipEventRecord");
+            HIP_TRY(launch_prepare(a2, stream), "prepare launch");
+            HIP_TRY(begin_timed(1), "hipEventRecord");
+            HIP_TRY(launch_persistent(a2, grid, stream), "persistent launch");
+            HIP_TRY(end_timed(1), "hipEventRecord");
         } else {
             GraphKey key{q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev,
                          n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, d.group16_max, grid, sw_words};
             auto it = w.graphs.find(key);
             if (it == w.graphs.end()) {
                 if (w.graphs.size() >= 16) {
-                    (void)hipGraphExecDestroy(w.graphs.begin()->second.prepare);
-                    (void)hipGraphExecDestroy(w.graphs.begin()->second.align);
+                    w.graphs.begin()->second.destroy();
                     w.graphs.erase(w.graphs.begin());
                 }
                 Workspace::Graphs gs;
-                rc = capture(d, [&](hipStream_t s) { return launch_prepare(a, s); }, &gs.prepare);
-                if (rc) return rc;
-                rc = capture(d, [&](hipStream_t s) { return launch_persistent(a, grid, s); }, &gs.align);
+                rc = capture(d, [&](hipStream_t st) { return launch_prepare(a1, st); }, &gs.g[0]);
+                if (!rc) rc = capture(d, [&](hipStream_t st) { return launch_persistent(a1, grid, st); }, &gs.g[1]);
+                if (!rc) rc = capture(d, [&](hipStream_t st) { return launch_prepare(a2, st); }, &gs.g[2]);
+                if (!rc) rc = capture(d, [&](hipStream_t st) { return launch_persistent(a2, grid, st); }, &gs.g[3]);
                 if (rc) {
-                    (void)hipGraphExecDestroy(gs.prepare);
+                    gs.destroy();
                     return rc;
                 }
                 it = w.graphs.emplace(key, gs).first;
             }
-            HIP_TRY(hipGraphLaunch(it->second.prepare, stream), "graph launch");
-            HIP_TRY(begin_timed(), "hipEventRecord");
-            HIP_TRY(hipGraphLaunch(it->second.align, stream), "graph launch");
-            HIP_TRY(end_timed(), "hipEventRecord");
+            const Workspace::Graphs& gs = it->second;
+            HIP_TRY(hipGraphLaunch(gs.g[0], stream), "graph launch");
+            HIP_TRY(begin_timed(0), "hipEventRecord");
+            HIP_TRY(hipGraphLaunch(gs.g[1], stream), "graph launch");
+            HIP_TRY(end_timed(0), "hipEventRecord");
+            HIP_TRY(hipGraphLaunch(gs.g[2], stream), "graph launch");
+            HIP_TRY(begin_timed(1), "hipEventRecord");
+            HIP_TRY(hipGraphLaunch(gs.g[3], stream), "graph launch");
+            HIP_TRY(end_timed(1), "hipEventRecord");
         }
+        finish_timed();
     }
     if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
     return SW_OK;
@@ -549,9 +588,10 @@ int sw_timing_read(void* stream_, double* kernel_ms, int64_t* calls)
         total += ms;
     }
     *kernel_ms = total;
-    *calls = (int64_t)w.timed.size();
+    *calls = w.timed_calls;
     for (auto& e : w.timed) w.event_pool.push_back(e);
     w.timed.clear();
+    w.timed_calls = 0;
     return SW_OK;
 }
 

@@ -909,7 +909,11 @@ __device__ __forceinline__ void write_result(sw_result* out, int pid, int S, int
     out[pid] = r;
 }
 
-// One work item: up to 64/P pairs, P lanes each.
+// One work item: up to 64/P pairs, P lanes each.  a.phase 0 runs the forward
+// pass and the start pass of each pair; phase 1 only the forward pass (score
+// and end written, starts -1); phase 2 only the start pass of pairs whose
+// score and end are already in `out` (the item then groups pairs by the size
+// of their start-pass region, so its lanes finish together).
 template <int R, int P, bool WIDE>
 __device__ __forceinline__ void do_group(const Args& a, int first, int count, uint8_t* lds, uint32_t* slot)
 {
@@ -919,6 +923,7 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     const int g = lane / P, u = lane % P;
     int pid = -1, m = 0, n = 0;
     int64_t qoff = 0, roff = 0;
+    Best f{0, -1, -1};  // forward result (read back in phase 2)
     if (g < count) {
         pid = a.perm[first + g];
         if (pid < 0 || pid >= a.n_pairs) pid = -1;
@@ -929,6 +934,20 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
         m = (int)(a.q_offsets[qi + 1] - qoff);
         roff = a.r_offsets[ri];
         n = (int)(a.r_offsets[ri + 1] - roff);
+        if (a.phase == 2) {
+            // the start pass covers q[0..q_end] x r[0..r_end]
+            const sw_result r = a.out[pid];
+            if (r.score > 0 && r.q_end >= 0 && r.q_end < m && r.r_end >= 0 && r.r_end < n) {
+                f = Best{r.score, r.q_end, r.r_end};
+                m = r.q_end + 1;
+                n = r.r_end + 1;
+            } else {
+                pid = -1;
+                m = n = 0;
+            }
+        }
+    }
+    if (pid >= 0) {
         // the slot must hold one boundary cell per column for every group
         // (narrow one- and 16-lane groups: three buffers of fixed size)
         const int64_t need = (int64_t)((n + 7) / 8) * G * SW * 4;
@@ -944,10 +963,25 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
             }
             pid = -1;
             m = n = 0;
+            f = Best{0, -1, -1};
         }
     }
     uint8_t* prof = lds;
     uint4* xbuf = reinterpret_cast<uint4*>(lds + kNumCodes * kWave * prof_bytes(R));
+    // forward pass done: phase 1 stores score and end, the start pass follows
+    // in phase 0
+    auto forward_done = [&](int packed_s) __attribute__((always_inline)) {
+        if (pid >= 0 && u == 0 && packed_s >= 0 && f.s != packed_s)
+            atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+        if (a.phase == 1 && pid >= 0 && u == 0) {
+            sw_result r;
+            r.score = f.s;
+            r.q_start = r.r_start = -1;
+            r.q_end = f.s > 0 ? f.i : -1;
+            r.r_end = f.s > 0 ? f.j : -1;
+            a.out[pid] = r;
+        }
+    };
     // packed score passes for every pair up to kMaxP16Len residues (the one-
     // and 16-lane groups only get such pairs; a whole wave takes the longest
     // of them and everything beyond, which runs in int32 throughout), then the
@@ -959,27 +993,34 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     }
     if (packed) {
         uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
-        const StripPick pf = packed_sweep<P, false>(a, prof, xw, slot, qoff, m, roff, n, 0);
-        const Best f = group_sweep<R, P, false, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, pf.ss,
-                                                            pf.buf);
-        const bool has = f.s > 0;
-        const int64_t qr = qoff + (has ? f.i : 0), rr = roff + (has ? f.j : 0);
-        const int mr = has ? f.i + 1 : 0, nr = has ? f.j + 1 : 0;
+        if (a.phase != 2) {
+            const StripPick pf = packed_sweep<P, false>(a, prof, xw, slot, qoff, m, roff, n, 0);
+            f = group_sweep<R, P, false, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, pf.ss, pf.buf);
+            forward_done(pf.s);
+            if (a.phase == 1) return;
+        }
+        const bool hs = f.s > 0;
+        const int64_t qr = qoff + (hs ? f.i : 0), rr = roff + (hs ? f.j : 0);
+        const int mr = hs ? f.i + 1 : 0, nr = hs ? f.j + 1 : 0;
         const StripPick pr = packed_sweep<P, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
         const Best r = group_sweep<R, P, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s,
-                                                           has ? pr.ss : -1, pr.buf);
+                                                           hs ? pr.ss : -1, pr.buf);
         if (pid >= 0 && u == 0) {
-            if (f.s != pf.s || (has && r.s != f.s)) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+            if (hs && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
             write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
         }
         return;
     }
-    const Best f = group_sweep<R, P, false, WIDE>(a, prof, xbuf, slot, qoff, m, roff, n, 0);
-    const bool has = f.s > 0;
-    const Best r = group_sweep<R, P, true, WIDE>(a, prof, xbuf, slot, qoff + (has ? f.i : 0), has ? f.i + 1 : 0,
-                                                 roff + (has ? f.j : 0), has ? f.j + 1 : 0, f.s);
+    if (a.phase != 2) {
+        f = group_sweep<R, P, false, WIDE>(a, prof, xbuf, slot, qoff, m, roff, n, 0);
+        forward_done(-1);
+        if (a.phase == 1) return;
+    }
+    const bool hs = f.s > 0;
+    const Best r = group_sweep<R, P, true, WIDE>(a, prof, xbuf, slot, qoff + (hs ? f.i : 0), hs ? f.i + 1 : 0,
+                                                 roff + (hs ? f.j : 0), hs ? f.j + 1 : 0, f.s);
     if (pid >= 0 && u == 0) {
-        if (has && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+        if (hs && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
         write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
     }
 }
@@ -1093,6 +1134,33 @@ __device__ __forceinline__ int cell_kind(int cell, int group16_max)
 // Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
 // (length bucket, 16*log2(m*n)).  Returns -1 for pairs that need no work and
 // -2 for invalid pairs (their result is written here).
+// Cell of a pair of lengths m, n > 0 (lane-per-pair cells by (strips,
+// chunks), longer pairs by (length bucket, 16*log2(m*n))).
+__device__ __forceinline__ int cell_of(const Args& a, int64_t m, int64_t n)
+{
+    const int64_t mx = m > n ? m : n;
+    if (mx <= a.inter_max_len) {
+        const int s = (int)((m + a.rows_per_lane - 1) / a.rows_per_lane);
+        const int c = (int)((n + 7) / 8);
+        return (s - 1) * kMaxInterChunks + (c - 1);
+    }
+    const int64_t cost = m * n;
+    const int msb = 63 - __clzll((unsigned long long)cost);
+    const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15) : 0;
+    const int cb = min(kWideCostBins - 1, 16 * msb + frac);
+    return kInterCells + ceil_log2(mx) * kWideCostBins + cb;
+}
+
+// Start-pass cell of a pair whose forward pass is done: by the reversed
+// prefixes q[0..q_end], r[0..r_end]; -1 when there is nothing to do (score 0,
+// or a pair the forward pass rejected).
+__device__ __forceinline__ int classify_start(const Args& a, int64_t k)
+{
+    const sw_result r = a.out[k];
+    if (r.score <= 0 || r.q_end < 0 || r.r_end < 0) return -1;
+    return cell_of(a, (int64_t)r.q_end + 1, (int64_t)r.r_end + 1);
+}
+
 __device__ __forceinline__ int classify(const Args& a, int64_t k)
 {
     const int64_t qi = a.pairs[2 * k], ri = a.pairs[2 * k + 1];
@@ -1116,17 +1184,7 @@ __device__ __forceinline__ int classify(const Args& a, int64_t k)
         a.out[k] = z;
         return -1;
     }
-    const int64_t mx = m > n ? m : n;
-    if (mx <= a.inter_max_len) {
-        const int s = (int)((m + a.rows_per_lane - 1) / a.rows_per_lane);
-        const int c = (int)((n + 7) / 8);
-        return (s - 1) * kMaxInterChunks + (c - 1);
-    }
-    const int64_t cost = m * n;
-    const int msb = 63 - __clzll((unsigned long long)cost);
-    const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15) : 0;
-    const int cb = min(kWideCostBins - 1, 16 * msb + frac);
-    return kInterCells + ceil_log2(mx) * kWideCostBins + cb;
+    return cell_of(a, m, n);
 }
 
 __global__ void k_fill(int32_t* p, int64_t n, int32_t v)
@@ -1146,7 +1204,7 @@ __global__ void k_prepare(Args a)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int cell = classify(a, k);
+        const int cell = a.phase == 2 ? classify_start(a, k) : classify(a, k);
         a.pair_cell[k] = cell;
         if (cell >= 0) atomicAdd(&a.cell_count[cell], 1);
         else if (cell == -2) atomicOr((unsigned*)a.err, (unsigned)kErrRange);

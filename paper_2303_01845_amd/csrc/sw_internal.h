@@ -91,6 +91,8 @@ struct Args {
     int32_t rows_per_lane;
     int32_t inter_max_len;
     int32_t group16_max_len;   // longest pair of a 16-lane group (power of two)
+    int32_t phase;             // 0: both passes per item; 1: forward pass only (writes score
+                               // and end); 2: start pass only (reads them from out)
 };
 
 // launchers (sw_device.hip); all asynchronous on `stream`

@@ -244,8 +244,18 @@ def test_timed_calls(sw):
     sw.timing_read(stream)
     for flags, label in [(0, "persistent+graph"), (sw.NO_GRAPH, "persistent"), (sw.PLAIN, "plain")]:
         say("timed, %s" % label)
+        outer = 0.0
         for _ in range(2):
-            assert_same(gpu_align(sw, ps, flags=flags | sw.TIMED), exp, ps, "timed " + label)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            got = gpu_align(sw, ps, flags=flags | sw.TIMED)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            outer += e0.elapsed_time(e1)
+            assert_same(got, exp, ps, "timed " + label)
         ms, calls = sw.timing_read(stream)
         assert calls == 2 and ms > 0.0, (label, ms, calls)
+        # the library's events sit inside the calls: their sum cannot exceed
+        # the time between events recorded around the calls
+        assert ms <= outer * 1.02 + 0.02, (label, ms, outer)
         assert sw.timing_read(stream) == (0.0, 0)
