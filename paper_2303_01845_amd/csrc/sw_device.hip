@@ -268,6 +268,7 @@ __device__ __forceinline__ uint32_t nib_score(const uint32_t (&w)[R / 8])
 // max(max(d, E), F) into a signed and an unsigned max instead of one
 // v_max3_i32.
 __device__ __forceinline__ void opaque(int& v) { asm("" : "+v"(v)); }
+__device__ __forceinline__ void opaque(uint32_t& v) { asm("" : "+v"(v)); }
 
 template <int R, int I>
 struct RowUnroll {
@@ -600,6 +601,10 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
 
+// The top boundary of a pair's first super-strip: read with a zero stride by
+// every lane (never written).
+__device__ uint4 g_zero_row[2];
+
 // Keeps the compiler from moving memory accesses across this point (LDS
 // hand-over between lanes of one wave; the hardware keeps a wave's LDS
 // accesses in order).
@@ -653,7 +658,9 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         }
         const bool read_top = ss > 0;
         const bool write_next = ss + 1 < my_ss;
-        const uint4* in4 = reinterpret_cast<const uint4*>(grp_slot + bi * BW);
+        // the first super-strip reads zeros (one 32-byte row for all chunks)
+        const uint4* in4 = read_top ? reinterpret_cast<const uint4*>(grp_slot + bi * BW) : g_zero_row;
+        const int in_stride = read_top ? G * 2 : 0;
         uint4* out4 = reinterpret_cast<uint4*>(grp_slot + bo * BW);
         uint32_t H[8], E[8], Mx[8];
 #pragma unroll
@@ -708,13 +715,14 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             hw_n = __builtin_amdgcn_alignbit(h1, h0, (uint32_t)(st & 31));
         };
         auto fetch = [&](int cn) __attribute__((always_inline)) {
-            // load from an index inside the pair's chunks, then select: the
-            // address is always valid and no select of addresses arises
-            const bool real = u == 0 && read_top && cn >= 0 && cn < my_chunks;
+            // an index inside the pair's chunks: the columns past the last
+            // chunk (padding, scored -4 against everything) get the last
+            // chunk's boundary, real cells of the row above, so their values
+            // stay below the pair's maximum.  Lanes u > 0 take their top
+            // row from lane u - 1 instead.
             const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
-            const uint4 v0 = in4[cc * (G * 2)], v1 = in4[cc * (G * 2) + 1];
-            tn0 = real ? v0 : make_uint4(0, 0, 0, 0);
-            tn1 = real ? v1 : make_uint4(0, 0, 0, 0);
+            tn0 = in4[cc * in_stride];
+            tn1 = in4[cc * in_stride + 1];
             if constexpr (P > 1) window8(rv, chunk_x(cn), nw_n, hw_n);
         };
         if constexpr (P == 1) {
@@ -785,11 +793,23 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 // low halves from this column's entry (A rows), high halves
                 // from the previous one (B rows): register i gets nibble i & 3
                 // of both
-                const uint32_t x0 = (pw0 & 0xFFFF0000u) | (w[0] & 0xFFFFu);
-                const uint32_t x1 = (pw1 & 0xFFFF0000u) | (w[1] & 0xFFFFu);
+                // (one v_bfi each; opaque keeps the masks below from being
+                // folded into it, which costs two more instructions)
+                uint32_t x0 = (pw0 & 0xFFFF0000u) | (w[0] & 0xFFFFu);
+                uint32_t x1 = (pw1 & 0xFFFF0000u) | (w[1] & 0xFFFFu);
+                opaque(x0);
+                opaque(x1);
                 uint32_t sw[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) sw[i] = ((i < 4 ? x0 : x1) >> (4 * (i & 3))) & 0x000F000Fu;
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t x = i < 4 ? x0 : x1;
+                    if ((i & 3) == 3) {  // the top nibble of each half: one packed shift
+                        const u16x2 t12 = {12, 12};
+                        sw[i] = as_u32(as_u16x2(x) >> t12);
+                    } else {
+                        sw[i] = (x >> (4 * (i & 3))) & 0x000F000Fu;
+                    }
+                }
                 // row 0 inputs: A from the row above at column t, B from A's
                 // row 7 at column t - 1
                 const uint32_t up_cur = __builtin_amdgcn_perm(H[7], top[k], 0x05040100u);
@@ -844,7 +864,8 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 mem_order();
             }
             // chunk c-1 of the bottom row is complete: columns 8c-8 .. 8c-2
-            // from the previous iteration, 8c-1 from this one
+            // from the previous iteration, 8c-1 from this one (whole 32-byte
+            // rows: split partial stores measured slower)
             if (u == P - 1 && act && write_next && c >= 1 && c - 1 < my_chunks) {
                 out4[(c - 1) * (G * 2)] = make_uint4(botp[1], botp[2], botp[3], botp[4]);
                 out4[(c - 1) * (G * 2) + 1] = make_uint4(botp[5], botp[6], botp[7], bq[0]);

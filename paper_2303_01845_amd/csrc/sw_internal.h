@@ -48,7 +48,7 @@ constexpr int kMaxInterChunks = 128;   // ceil(inter_max_len / 8) <= this
 constexpr int kMaxInterLen = 1024;
 constexpr int kMaxP16Len = 4096;      // longest pair a 16-lane group may get; the packed
                                       // 16-bit pass also covers whole waves up to this
-constexpr int kDefaultGroup16Max = 2048;  // default group16_max_len
+constexpr int kDefaultGroup16Max = 4096;  // default group16_max_len
 constexpr int kXbufBytes = 64 * 96;   // LDS exchange / staging buffer: 24 words per lane
 constexpr int kWideCostBins = 512;     // floor(16 * log2(m*n)) for long (wide) pairs
 constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
