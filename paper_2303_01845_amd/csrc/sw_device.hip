@@ -725,13 +725,19 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             tn1 = in4[cc * in_stride + 1];
             if constexpr (P > 1) window8(rv, chunk_x(cn), nw_n, hw_n);
         };
+        fetch(-u);
         if constexpr (P == 1) {
             load_batch(0);
             store_batch();
+        }
+        // Nothing in flight when the chunk loop starts: a load still pending
+        // on entry makes the compiler keep waits for it inside the loop,
+        // which then stall on the loads issued in the same iteration.
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        if constexpr (P == 1) {
             load_batch(1);
             window_lds(0);
         }
-        fetch(-u);
         // Iteration t: lane u on chunk c = t - u, A on columns 8c .. 8c+7,
         // B on 8c-1 .. 8c+6.  Each lane needs my_chunks + 1 chunk iterations
         // (the last one for B's final column); the very last iteration of the
@@ -844,6 +850,16 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 *x_mid = bq[0];  // column 8c - 1, for lane u + 1's chunk c - 1
                 mem_order();
             }
+            // chunk c-1 of the bottom row is complete: columns 8c-8 .. 8c-2
+            // from the previous iteration, 8c-1 from this one's first step.
+            // Stored here, early: stores and loads share one counter, so a
+            // store still in flight at the end of the iteration would hold
+            // up the wait for the next chunk's loads.  (Whole 32-byte rows:
+            // split partial stores measured slower.)
+            if (u == P - 1 && act && write_next && c >= 1 && c - 1 < my_chunks) {
+                out4[(c - 1) * (G * 2)] = make_uint4(botp[1], botp[2], botp[3], botp[4]);
+                out4[(c - 1) * (G * 2) + 1] = make_uint4(botp[5], botp[6], botp[7], bq[0]);
+            }
             if (act) {
 #pragma unroll
                 for (int k = 1; k < STEPS; ++k) {
@@ -862,13 +878,6 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 reinterpret_cast<uint4*>(x_end)[0] = make_uint4(bq[1], bq[2], bq[3], bq[4]);
                 reinterpret_cast<uint4*>(x_end)[1] = make_uint4(bq[5], bq[6], bq[7], 0u);
                 mem_order();
-            }
-            // chunk c-1 of the bottom row is complete: columns 8c-8 .. 8c-2
-            // from the previous iteration, 8c-1 from this one (whole 32-byte
-            // rows: split partial stores measured slower)
-            if (u == P - 1 && act && write_next && c >= 1 && c - 1 < my_chunks) {
-                out4[(c - 1) * (G * 2)] = make_uint4(botp[1], botp[2], botp[3], botp[4]);
-                out4[(c - 1) * (G * 2) + 1] = make_uint4(botp[5], botp[6], botp[7], bq[0]);
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) botp[k] = bq[k];
