@@ -377,6 +377,10 @@ __host__ __device__ constexpr int64_t boundary_buf_words(int P)
 // groups; -1 for none), reading its input row from boundary buffer `one_buf`
 // of the slot and writing nothing: the exact-cell pass after the packed
 // score pass.
+// The top boundary of a pair's first super-strip: read with a zero stride by
+// every lane (never written; one chunk of the widest boundary format).
+__device__ uint4 g_zero_row[4];
+
 template <int R, int P, bool REV, bool WIDE, bool ONE = false>
 __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t* __restrict__ slot,
                             int64_t Q0, int M, int64_t R0, int N, int target, int one_ss = -1, int one_buf = 0)
@@ -452,19 +456,32 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
         // LDS before column k is computed, so neither latency sits in front of
         // the cell updates.  Idle steps (before the first or past the last
         // chunk) still load, so their indexes are kept inside the pair.
+        // No value of a load is used in the iteration that issues it (a
+        // select on it, or the window's alignment, would wait for the load
+        // right there): the first super-strip reads a zero row with stride 0,
+        // padding columns read the last real chunk (real cells of the row
+        // above, so padding stays below the pair's maximum), lanes u > 0
+        // take the row from lane u - 1 instead, and the window words are
+        // aligned where they are used.
+        const uint4* in4 = read_top ? slot4 : g_zero_row;
+        const int in_stride = read_top ? G * SW : 0;
         uint4 tc_n[SW];
-        uint32_t nw_n, hw_n;
+        uint32_t na_n, nb_n, ha_n, hb_n;
+        int q_n;
         auto fetch = [&](int cn) {
-            // load, then select (a select of addresses would become a flat load)
             const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
 #pragma unroll
-            for (int w = 0; w < SW; ++w) {
-                const uint4 v = slot4[cc * G * SW + w];
-                tc_n[w] = (u == 0 && read_top) ? v : make_uint4(0, 0, 0, 0);
-            }
-            window8(rv, chunk_x(cn), nw_n, hw_n);
+            for (int w = 0; w < SW; ++w) tc_n[w] = in4[cc * in_stride + w];
+            const int q = rv.off + chunk_x(cn);
+            na_n = rv.nib[q >> 3];
+            nb_n = rv.nib[(q >> 3) + 1];
+            ha_n = rv.hib[q >> 5];
+            hb_n = rv.hib[(q >> 5) + 1];
+            q_n = q;
         };
         fetch(-u);
+        // nothing in flight on loop entry (see packed_sweep)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll 1
         for (int t = 0; t < T; ++t) {
             const int c = t - u;
@@ -472,7 +489,8 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
             uint4 tc[SW];
 #pragma unroll
             for (int w = 0; w < SW; ++w) tc[w] = u == 0 ? tc_n[w] : x_up[w];
-            uint32_t nw = nw_n, hw = hw_n;
+            uint32_t nw = __builtin_amdgcn_alignbit(nb_n, na_n, (uint32_t)(q_n & 7) * 4u);
+            uint32_t hw = __builtin_amdgcn_alignbit(hb_n, ha_n, (uint32_t)(q_n & 31));
             if (t + 1 < T) fetch(c + 1);
             uint32_t bot[4 * SW];
 #pragma unroll
@@ -600,10 +618,6 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
-
-// The top boundary of a pair's first super-strip: read with a zero stride by
-// every lane (never written).
-__device__ uint4 g_zero_row[2];
 
 // Keeps the compiler from moving memory accesses across this point (LDS
 // hand-over between lanes of one wave; the hardware keeps a wave's LDS
