@@ -787,9 +787,14 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 window_lds(c + 1);
             }
             if (t + 1 <= wc + P - 1) fetch(c + 1);
+            // B's row 15 per step.  An idle lane hands zeros to lane u + 1;
+            // with one lane per pair the values are only read after an
+            // active iteration, so nothing is cleared.
             uint32_t bq[8];
+            if constexpr (P > 1) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) bq[k] = 0;
+                for (int k = 0; k < 8; ++k) bq[k] = 0;
+            }
             const int valid = min(max(N - 8 * c, 0), 8);
             if (valid < 8) {
                 if (REV) {
