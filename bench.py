@@ -27,6 +27,13 @@ PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_PACKED16_TOPS = 2 * PEAK_INT32_TOPS
 ALGO_OPS_PER_CELL = 8  # sub, 2x(sub,max) for E and F, add, max3, running max
 
+# name -> (generator, default pairs, length description)
+WORKLOADS = {
+    "1m-lognormal280": ("config_1m", 1_000_000, "lognormal median 280 sigma 0.6 clipped 30-5000"),
+    "heavy-tail": ("config_batching", 20_000, "95% lognormal median 250 sigma 0.6, 5% uniform 5000-35000"),
+    "block-50kx50k": ("config_block", 0, "2000 families, lognormal median 280; candidates share >= 2 6-mers"),
+}
+
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -37,7 +44,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--pairs", type=int, default=1_000_000)
+    ap.add_argument("--workload", default="1m-lognormal280", choices=sorted(WORKLOADS),
+                    help="synthetic workload (the default is the headline one)")
+    ap.add_argument("--pairs", type=int, default=0, help="pairs (0: the workload's own size)")
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -82,7 +91,9 @@ def main():
     tuning = sw.get_tuning()
 
     t0 = time.time()
-    ps = P.config_1m(args.pairs)
+    gen, default_pairs, lengths_desc = WORKLOADS[args.workload]
+    n_pairs = args.pairs or default_pairs
+    ps = getattr(P, gen)(n_pairs) if n_pairs else getattr(P, gen)()
     cells = ps.cells()
     log("generated %d pairs, %d sequences, %.3f Gcells in %.1fs" % (ps.n_pairs, ps.n_seqs, cells / 1e9,
                                                                    time.time() - t0))
@@ -196,9 +207,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u16x2+i32",
         "data": "synthetic",
-        "config": {"workload": "1m-lognormal280", "pairs": ps.n_pairs, "sequences": ps.n_seqs,
+        "config": {"workload": args.workload, "pairs": ps.n_pairs, "sequences": ps.n_seqs,
                    "cells": cells, "scoring": "BLOSUM62 gap_open 11 gap_extend 1",
-                   "lengths": "lognormal median 280 sigma 0.6 clipped 30-5000",
+                   "lengths": lengths_desc,
                    "tuning": tuning},
         "alignments_per_s": round(aps, 1),
         "align_ms": round(align_ms, 3),
@@ -209,7 +220,7 @@ def main():
         "parity_sample": "%d/%d bit-exact vs CPU oracle" % (n_ok, len(sample)),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_PACKED16_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved / PEAK_PACKED16_TOPS, 4),
-                     "traffic": stored_traffic(R, ps.n_pairs),
+                     "traffic": stored_traffic(R, ps.n_pairs) if args.workload == "1m-lognormal280" else None,
                      "kernel": "k_persistent<%d>, %d ops per cell x %d cells per step; two launches per "
                                "step (forward, start), mean launch %.3f ms" % (
                                    R, ALGO_OPS_PER_CELL, cells, kernel_ms / 2),

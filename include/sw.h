@@ -166,8 +166,9 @@ SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
  * 64 rows_per_lane) that is aligned one pair per lane; longer pairs up to
  * group16_max_len (a power of two, 64..4096) are spread over a group of 16
  * lanes, longer ones over a whole 64-lane wave; blocks_per_cu sets the
- * persistent grid (1..8).  Any field <= 0 keeps the current value.  Results
- * never depend on these values.
+ * persistent grid (1..8; -1 goes back to the occupancy-derived value, which
+ * is the default).  A field of 0 (and any other field <= 0) keeps the current
+ * value.  Results never depend on these values.
  */
 typedef struct {
     int32_t rows_per_lane;

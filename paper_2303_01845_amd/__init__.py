@@ -197,6 +197,7 @@ def timing_read(stream=None):
 
 def set_tuning(rows_per_lane: int = 0, inter_max_len: int = 0, blocks_per_cu: int = 0,
                group16_max_len: int = 0):
+    """0 keeps a field; blocks_per_cu -1 returns to the occupancy-derived grid."""
     _check(lib().sw_set_tuning(ctypes.byref(Tuning(rows_per_lane, inter_max_len, blocks_per_cu,
                                                    group16_max_len))), "sw_set_tuning")
 

@@ -603,7 +603,7 @@ int sw_set_tuning(const sw_tuning* t)
     if (t->rows_per_lane > 0 && t->inter_max_len > 0 &&
         (t->inter_max_len + t->rows_per_lane - 1) / t->rows_per_lane > kMaxInterStrips)
         return SW_EINVAL;
-    if (t->blocks_per_cu > 8) return SW_EINVAL;
+    if (t->blocks_per_cu > 8 || t->blocks_per_cu < -1) return SW_EINVAL;
     if (t->group16_max_len > 0 && (t->group16_max_len < 64 || t->group16_max_len > kMaxP16Len ||
                                    (t->group16_max_len & (t->group16_max_len - 1)) != 0))
         return SW_EINVAL;
@@ -621,6 +621,7 @@ int sw_set_tuning(const sw_tuning* t)
     d->inter_max = im;
     d->group16_max = g16;
     if (t->blocks_per_cu > 0) d->bpc_user = t->blocks_per_cu;
+    else if (t->blocks_per_cu == -1) d->bpc_user = 0;  // occupancy-derived
     if (reorder) {
         rc = upload_ordering(*d);
         if (rc) return rc;

@@ -22,7 +22,7 @@ def sw():
     assert torch.cuda.is_available(), "no GPU"
     import paper_2303_01845_amd as lib
     lib.lib()
-    lib.set_tuning(16, 1024, 0, 2048)
+    lib.set_tuning(16, 1024, -1, 4096)
     return lib
 
 
@@ -157,7 +157,7 @@ def test_tuning_does_not_change_results(sw):
                 assert_same(got, expect(ps), ps, "tuning reference")
             assert (got == ref).all(), (R, im, bpc)
     finally:
-        sw.set_tuning(16, 1024, 0, 2048)
+        sw.set_tuning(16, 1024, -1, 4096)
 
 
 def test_permuted_pairs(sw):
