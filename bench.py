@@ -300,7 +300,7 @@ def serve_bench(args):
         "n_gpus": 1,
         "higher_is_better": False,
         "data": "synthetic",
-        "dtype": "int32",
+        "dtype": "u16x2+i32",
         "config": {"workload": "serve-families%dx50" % args.serve_families, "requests": n,
                    "max_batch": args.serve_max_batch, "slots": args.serve_slots, "hbm_budget_gib": 16,
                    "candidates": "refs sharing >= 2 distinct 6-mers, top 200 per query",
