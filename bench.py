@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--inter-max", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--group16-max", type=int, default=0)
+    ap.add_argument("--group8-max", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner on the workload before timing")
     ap.add_argument("--no-graph", action="store_true",
@@ -86,8 +87,8 @@ def main():
         serve_bench(args)
         return
     sw.lib()
-    if args.rows_per_lane or args.inter_max or args.blocks_per_cu or args.group16_max:
-        sw.set_tuning(args.rows_per_lane, args.inter_max, args.blocks_per_cu, args.group16_max)
+    if args.rows_per_lane or args.inter_max or args.blocks_per_cu or args.group16_max or args.group8_max:
+        sw.set_tuning(args.rows_per_lane, args.inter_max, args.blocks_per_cu, args.group16_max, args.group8_max)
     tuning = sw.get_tuning()
 
     t0 = time.time()

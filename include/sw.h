@@ -164,8 +164,11 @@ SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
  * the number of query rows each lane keeps in registers (8 or 16);
  * inter_max_len is the longest pair (max of both lengths, 64..1024, at most
  * 64 rows_per_lane) that is aligned one pair per lane; longer pairs up to
- * group16_max_len (a power of two, 64..4096) are spread over a group of 16
- * lanes, longer ones over a whole 64-lane wave; blocks_per_cu sets the
+ * group8_max_len are spread over a group of 8 lanes, longer ones up to
+ * group16_max_len over a group of 16 lanes (both powers of two, 64..4096;
+ * both 2048 by default, which leaves no pair to 16-lane groups: a 4096-residue
+ * pair on 16 lanes outlasts the rest of a launch), longer ones over a whole
+ * 64-lane wave; blocks_per_cu sets the
  * persistent grid (1..8; -1 goes back to the occupancy-derived value, which
  * is the default).  A field of 0 (and any other field <= 0) keeps the current
  * value.  Results never depend on these values.
@@ -175,6 +178,7 @@ typedef struct {
     int32_t inter_max_len;
     int32_t blocks_per_cu;
     int32_t group16_max_len;
+    int32_t group8_max_len;
 } sw_tuning;
 SW_API int sw_set_tuning(const sw_tuning* t);
 SW_API int sw_get_tuning(sw_tuning* t);
@@ -183,7 +187,8 @@ SW_API int sw_get_tuning(sw_tuning* t);
  * Autotuner: time sw_batch_align (persistent form) on this workload for every
  * candidate kernel shape (rows_per_lane 16/8, inter_max_len 512/768/1024 --
  * the length above which a pair gets a lane group instead of one lane --,
- * group16_max_len 1024/2048/4096, blocks_per_cu occupancy-derived), `reps`
+ * group8_max_len 1024/2048, group16_max_len 2048/4096, blocks_per_cu
+ * occupancy-derived), `reps`
  * timed runs each, require
  * every shape to give byte-identical results, keep the fastest as the current
  * tuning and report it in *chosen (and its time per call in *best_ms, may be

@@ -56,7 +56,8 @@ class Scoring(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("inter_max_len", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("group16_max_len", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("group16_max_len", ctypes.c_int32),
+                ("group8_max_len", ctypes.c_int32)]
 
 
 _lib = None
@@ -196,17 +197,18 @@ def timing_read(stream=None):
 
 
 def set_tuning(rows_per_lane: int = 0, inter_max_len: int = 0, blocks_per_cu: int = 0,
-               group16_max_len: int = 0):
+               group16_max_len: int = 0, group8_max_len: int = 0):
     """0 keeps a field; blocks_per_cu -1 returns to the occupancy-derived grid."""
     _check(lib().sw_set_tuning(ctypes.byref(Tuning(rows_per_lane, inter_max_len, blocks_per_cu,
-                                                   group16_max_len))), "sw_set_tuning")
+                                                   group16_max_len, group8_max_len))), "sw_set_tuning")
 
 
 def get_tuning() -> dict:
     t = Tuning()
     _check(lib().sw_get_tuning(ctypes.byref(t)), "sw_get_tuning")
     return {"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
-            "blocks_per_cu": t.blocks_per_cu, "group16_max_len": t.group16_max_len}
+            "blocks_per_cu": t.blocks_per_cu, "group16_max_len": t.group16_max_len,
+            "group8_max_len": t.group8_max_len}
 
 
 def autotune(packed, offsets, pairs, gap_open: int = 11, gap_extend: int = 1, reps: int = 3,
@@ -225,7 +227,8 @@ def autotune(packed, offsets, pairs, gap_open: int = 11, gap_extend: int = 1, re
                              ctypes.byref(sc), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), int(reps),
                              ctypes.byref(t), ctypes.byref(ms)), "sw_autotune")
     return ({"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
-             "blocks_per_cu": t.blocks_per_cu, "group16_max_len": t.group16_max_len}, float(ms.value))
+             "blocks_per_cu": t.blocks_per_cu, "group16_max_len": t.group16_max_len,
+             "group8_max_len": t.group8_max_len}, float(ms.value))
 
 
 def matrix():

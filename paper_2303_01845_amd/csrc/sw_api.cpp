@@ -49,11 +49,11 @@ int ceil_log2(int64_t x)
     return b;
 }
 
-Ordering make_ordering(int R, int inter_max, int group16_max)
+Ordering make_ordering(int R, int inter_max, int group8_max, int group16_max)
 {
     struct Key {
         int cell;
-        int kind;  // lanes per pair: 64, 16 or 1
+        int kind;  // lanes per pair: 64, 16, 8 or 1
         int bucket;
         int64_t cost;
         int s, c;
@@ -77,7 +77,8 @@ Ordering make_ordering(int R, int inter_max, int group16_max)
         for (int cb = 0; cb < kWideCostBins; ++cb) {
             Key k;
             k.cell = kInterCells + b * kWideCostBins + cb;
-            k.kind = ((int64_t)1 << b) <= std::min(group16_max, kMaxP16Len) ? 16 : 64;
+            const int64_t len = (int64_t)1 << b;
+            k.kind = len <= std::min(group8_max, kMaxP16Len) ? 8 : len <= std::min(group16_max, kMaxP16Len) ? 16 : 64;
             k.bucket = b;
             k.cost = cb;
             k.s = k.c = 0;
@@ -124,14 +125,14 @@ struct GraphKey {
     int64_t n_pairs;
     int32_t go, ge;
     void* out;
-    int R, inter_max, group16_max, grid;
+    int R, inter_max, group8_max, group16_max, grid;
     int64_t slot_words;
     bool operator<(const GraphKey& o) const
     {
         return std::tie(q_packed, q_offsets, n_q, r_packed, r_offsets, n_r, pairs, n_pairs, go, ge, out, R,
-                        inter_max, group16_max, grid, slot_words) <
+                        inter_max, group8_max, group16_max, grid, slot_words) <
                std::tie(o.q_packed, o.q_offsets, o.n_q, o.r_packed, o.r_offsets, o.n_r, o.pairs, o.n_pairs, o.go,
-                        o.ge, o.out, o.R, o.inter_max, o.group16_max, o.grid, o.slot_words);
+                        o.ge, o.out, o.R, o.inter_max, o.group8_max, o.group16_max, o.grid, o.slot_words);
     }
 };
 
@@ -198,6 +199,7 @@ struct Device {
     int R = 16;
     int inter_max = 1024;
     int group16_max = kDefaultGroup16Max;
+    int group8_max = kDefaultGroup8Max;
     int bpc_user = 0;  // 0: occupancy-derived
     Ordering ord;
     int32_t* rank_cell_persistent = nullptr;
@@ -212,7 +214,7 @@ std::map<int, std::unique_ptr<Device>> g_devices;
 
 int upload_ordering(Device& d)
 {
-    d.ord = make_ordering(d.R, d.inter_max, d.group16_max);
+    d.ord = make_ordering(d.R, d.inter_max, d.group8_max, d.group16_max);
     HIP_TRY(hipMemcpy(d.rank_cell_persistent, d.ord.rank_cell_persistent.data(), sizeof(int32_t) * kNumCells,
                       hipMemcpyHostToDevice),
             "upload ordering");
@@ -444,6 +446,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     a.rows_per_lane = d.R;
     a.inter_max_len = d.inter_max;
     a.group16_max_len = d.group16_max;
+    a.group8_max_len = d.group8_max;
 
     const bool timed = flags & SW_TIMED;
     std::pair<hipEvent_t, hipEvent_t> ev[2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -517,7 +520,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             HIP_TRY(end_timed(1), "hipEventRecord");
         } else {
             GraphKey key{q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev,
-                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, d.group16_max, grid, sw_words};
+                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, d.group8_max, d.group16_max, grid, sw_words};
             auto it = w.graphs.find(key);
             if (it == w.graphs.end()) {
                 if (w.graphs.size() >= 16) {
@@ -604,9 +607,8 @@ int sw_set_tuning(const sw_tuning* t)
         (t->inter_max_len + t->rows_per_lane - 1) / t->rows_per_lane > kMaxInterStrips)
         return SW_EINVAL;
     if (t->blocks_per_cu > 8 || t->blocks_per_cu < -1) return SW_EINVAL;
-    if (t->group16_max_len > 0 && (t->group16_max_len < 64 || t->group16_max_len > kMaxP16Len ||
-                                   (t->group16_max_len & (t->group16_max_len - 1)) != 0))
-        return SW_EINVAL;
+    for (int g : {t->group16_max_len, t->group8_max_len})
+        if (g > 0 && (g < 64 || g > kMaxP16Len || (g & (g - 1)) != 0)) return SW_EINVAL;
     std::lock_guard<std::mutex> lock(g_mutex);
     Device* d = nullptr;
     int rc = get_device(&d);
@@ -615,11 +617,13 @@ int sw_set_tuning(const sw_tuning* t)
     const int im = t->inter_max_len > 0 ? t->inter_max_len : d->inter_max;
     if ((im + R - 1) / R > kMaxInterStrips) return SW_EINVAL;
     const int g16 = t->group16_max_len > 0 ? t->group16_max_len : d->group16_max;
-    const bool reorder = R != d->R || im != d->inter_max || g16 != d->group16_max;
+    const int g8 = t->group8_max_len > 0 ? t->group8_max_len : d->group8_max;
+    const bool reorder = R != d->R || im != d->inter_max || g16 != d->group16_max || g8 != d->group8_max;
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     d->R = R;
     d->inter_max = im;
     d->group16_max = g16;
+    d->group8_max = g8;
     if (t->blocks_per_cu > 0) d->bpc_user = t->blocks_per_cu;
     else if (t->blocks_per_cu == -1) d->bpc_user = 0;  // occupancy-derived
     if (reorder) {
@@ -641,6 +645,7 @@ int sw_get_tuning(sw_tuning* t)
     t->inter_max_len = d->inter_max;
     t->blocks_per_cu = blocks_per_cu(*d);
     t->group16_max_len = d->group16_max;
+    t->group8_max_len = d->group8_max;
     return SW_OK;
 }
 
@@ -661,14 +666,21 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
     sw_tuning orig{};
     int rc = sw_get_tuning(&orig);
     if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        Device* d = nullptr;
+        if ((rc = get_device(&d))) return rc;
+        if (d->bpc_user == 0) orig.blocks_per_cu = -1;  // restore the occupancy-derived grid
+    }
     struct Cand {
-        int R, im, bpc, g16;
+        int R, im, g8, g16;
     };
     std::vector<Cand> cands;
     for (int R : {16, 8})
         for (int im : {512, 768, 1024})
-            for (int g16 : {1024, 2048, 4096})
-                if ((im + R - 1) / R <= kMaxInterStrips) cands.push_back({R, im, 0, g16});
+            for (int g8 : {1024, 2048})
+                for (int g16 : {2048, 4096})
+                    if ((im + R - 1) / R <= kMaxInterStrips) cands.push_back({R, im, g8, g16});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
@@ -677,13 +689,7 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
     sw_tuning best_t = orig;
     bool have_ref = false;
     for (const Cand& c : cands) {
-        sw_tuning t{c.R, c.im, c.bpc, c.g16};
-        if (c.bpc == 0) {  // back to the occupancy-derived grid
-            std::lock_guard<std::mutex> lock(g_mutex);
-            Device* d = nullptr;
-            if ((rc = get_device(&d))) break;
-            d->bpc_user = 0;
-        }
+        sw_tuning t{c.R, c.im, -1, c.g16, c.g8};  // occupancy-derived grid
         if ((rc = sw_set_tuning(&t))) break;
         // warm-up run, also the tile-independence check
         if ((rc = sw_batch_align(packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, scoring, out_dev, stream, 0)))
@@ -699,8 +705,9 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
             have_ref = true;
         } else if (std::memcmp(ref.data(), cur.data(), sizeof(sw_result) * (size_t)n_pairs) != 0) {
             std::snprintf(g_last_error, sizeof(g_last_error),
-                          "autotune: results differ between kernel shapes (R=%d inter_max=%d group16_max=%d)",
-                          c.R, c.im, c.g16);
+                          "autotune: results differ between kernel shapes (R=%d inter_max=%d group8_max=%d "
+                          "group16_max=%d)",
+                          c.R, c.im, c.g8, c.g16);
             rc = SW_EDEVICE;
             break;
         }
@@ -727,14 +734,10 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
         (void)sw_set_tuning(&orig);
         return rc;
     }
-    if (best_t.blocks_per_cu == 0) {
-        std::lock_guard<std::mutex> lock(g_mutex);
-        Device* d = nullptr;
-        if (get_device(&d) == SW_OK) d->bpc_user = 0;
-    }
     rc = sw_set_tuning(&best_t);
     if (rc) return rc;
-    *chosen = best_t;
+    rc = sw_get_tuning(chosen);
+    if (rc) return rc;
     if (best_ms) *best_ms = best;
     return SW_OK;
 }

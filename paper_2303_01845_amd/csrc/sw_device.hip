@@ -19,12 +19,13 @@
 // recurrence: by induction E_sat = max(E, 0), and H only uses max(0, E).
 //
 // Work decomposition.  Pairs up to 1024 residues get one lane each, longer
-// ones up to 4096 a group of 16 lanes, longer still a whole wave.  A lane
+// ones up to 2048 a group of 8 lanes, up to 4096 a group of 16 lanes, longer
+// still a whole wave (the limits are tunable).  A lane
 // keeps R query rows in registers and sweeps the reference in chunks of 8
 // columns; a group of P lanes covers a super-strip of P R rows as a
 // wavefront, and super-strips hand their bottom row to the next one through a
 // per-block scratch slot.  Scores come from a per-lane query profile in LDS.
-// The one- and 16-lane paths first run a packed 16-bit pass (two cells per
+// The one-, 8- and 16-lane paths first run a packed 16-bit pass (two cells per
 // instruction) that only finds the best score and the super-strip holding its
 // first cell, then recompute that super-strip in int32 with cell trackers;
 // the whole-wave path ("wide": any length, two dwords per boundary cell,
@@ -593,7 +594,7 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
 }
 
 // ------------------------------------------------------------------ packed 16-bit score pass
-// Groups of P lanes per pair (P = 1 or 16) with 16 rows per lane, two cells
+// Groups of P lanes per pair (P = 1, 8 or 16) with 16 rows per lane, two cells
 // per 32-bit register: lane u of a group holds rows 16 P ss + 16 u + 0..7
 // (half A) in the low 16 bits and rows + 8..15 (half B) in the high 16 bits,
 // and B runs one column behind A, so at each step A updates column t and B
@@ -998,7 +999,7 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     }
     if (pid >= 0) {
         // the slot must hold one boundary cell per column for every group
-        // (narrow one- and 16-lane groups: three buffers of fixed size)
+        // (narrow one-, 8- and 16-lane groups: three buffers of fixed size)
         const int64_t need = (int64_t)((n + 7) / 8) * G * SW * 4;
         const bool may_pack = R == 16 && (P == 64 ? max(m, n) <= kMaxP16Len : !WIDE);
         const int max_chunks = P == 1 ? kMaxInterChunks : kMaxP16Len / 8;
@@ -1031,8 +1032,8 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
             a.out[pid] = r;
         }
     };
-    // packed score passes for every pair up to kMaxP16Len residues (the one-
-    // and 16-lane groups only get such pairs; a whole wave takes the longest
+    // packed score passes for every pair up to kMaxP16Len residues (the one-,
+    // 8- and 16-lane groups only get such pairs; a whole wave takes the longest
     // of them and everything beyond, which runs in int32 throughout), then the
     // exact cells from one int32 super-strip each
     bool packed = false;
@@ -1086,9 +1087,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     // can never index past the permutation
     const int n64 = min(max(a.counters[kCntP64], 0), (int)a.n_pairs);
     const int n16 = min(max(a.counters[kCntP16], 0), (int)a.n_pairs - n64);
-    const int n1 = min(max(a.counters[kCntP1], 0), (int)a.n_pairs - n64 - n16);
-    const int i16 = (n16 + 3) / 4, i1 = (n1 + kWave - 1) / kWave;
-    const int total = n64 + i16 + i1;
+    const int n8 = min(max(a.counters[kCntP8], 0), (int)a.n_pairs - n64 - n16);
+    const int n1 = min(max(a.counters[kCntP1], 0), (int)a.n_pairs - n64 - n16 - n8);
+    const int i16 = (n16 + 3) / 4, i8 = (n8 + 7) / 8, i1 = (n1 + kWave - 1) / kWave;
+    const int total = n64 + i16 + i8 + i1;
 #pragma unroll 1
     for (;;) {
         int item = 0;
@@ -1100,9 +1102,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
         } else if (item < n64 + i16) {
             const int k = item - n64;
             do_group<R, 16, false>(a, n64 + 4 * k, min(4, n16 - 4 * k), lds, slot);
-        } else {
+        } else if (item < n64 + i16 + i8) {
             const int k = item - n64 - i16;
-            do_group<R, 1, false>(a, n64 + n16 + kWave * k, min(kWave, n1 - kWave * k), lds, slot);
+            do_group<R, 8, false>(a, n64 + n16 + 8 * k, min(8, n8 - 8 * k), lds, slot);
+        } else {
+            const int k = item - n64 - i16 - i8;
+            do_group<R, 1, false>(a, n64 + n16 + n8 + kWave * k, min(kWave, n1 - kWave * k), lds, slot);
         }
     }
 }
@@ -1171,12 +1176,14 @@ __device__ __forceinline__ int ceil_log2(int64_t x)
     return b;
 }
 
-// Lanes per pair of a work cell: 1 for the short-pair cells, 16 for long
-// pairs up to kMaxP16Len residues, 64 beyond.
-__device__ __forceinline__ int cell_kind(int cell, int group16_max)
+// Lanes per pair of a work cell: 1 for the short-pair cells; for long pairs
+// by length bucket 8 up to group8_max, 16 up to group16_max (both at most
+// kMaxP16Len residues), 64 beyond.
+__device__ __forceinline__ int cell_kind(int cell, int group8_max, int group16_max)
 {
     if (cell < kInterCells) return 1;
     const int bucket = (cell - kInterCells) / kWideCostBins;
+    if ((1 << bucket) <= min(group8_max, kMaxP16Len)) return 8;
     return (1 << bucket) <= min(group16_max, kMaxP16Len) ? 16 : 64;
 }
 
@@ -1267,30 +1274,35 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
     __shared__ int part[1024];
     __shared__ int n64s[1024];
     __shared__ int n16s[1024];
+    __shared__ int n8s[1024];
     const int t = threadIdx.x;
     constexpr int per = (kNumCells + 1023) / 1024;
     const int lo = t * per, hi = min(kNumCells, lo + per);
-    int sum = 0, c64 = 0, c16 = 0;
+    int sum = 0, c64 = 0, c16 = 0, c8 = 0;
     for (int rk = lo; rk < hi; ++rk) {
         const int cell = a.rank_cell[rk];
         const int c = a.cell_count[cell];
         sum += c;
-        const int kind = cell_kind(cell, a.group16_max_len);
+        const int kind = cell_kind(cell, a.group8_max_len, a.group16_max_len);
         if (kind == 64) c64 += c;
         else if (kind == 16) c16 += c;
+        else if (kind == 8) c8 += c;
     }
     part[t] = sum;
     n64s[t] = c64;
     n16s[t] = c16;
+    n8s[t] = c8;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
         const int v = t >= o ? part[t - o] : 0;
         const int w = t >= o ? n64s[t - o] : 0;
         const int x = t >= o ? n16s[t - o] : 0;
+        const int y = t >= o ? n8s[t - o] : 0;
         __syncthreads();
         part[t] += v;
         n64s[t] += w;
         n16s[t] += x;
+        n8s[t] += y;
         __syncthreads();
     }
     int run = part[t] - sum;  // exclusive prefix
@@ -1305,7 +1317,8 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
         a.rank_start[kNumCells] = part[1023];
         a.counters[kCntP64] = n64s[1023];
         a.counters[kCntP16] = n16s[1023];
-        a.counters[kCntP1] = part[1023] - n64s[1023] - n16s[1023];
+        a.counters[kCntP8] = n8s[1023];
+        a.counters[kCntP1] = part[1023] - n64s[1023] - n16s[1023] - n8s[1023];
     }
 }
 
@@ -1324,12 +1337,13 @@ size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * prof_bytes(R) + kXb
 int64_t slot_words()
 {
     // [chunk][group][8 cells]: 64 groups of one lane over at most 128 chunks
-    // (narrow, three buffers), 4 groups over 512 chunks (16 lanes, narrow), 1
-    // group over 8192 chunks (64 lanes, wide, two words per cell)
+    // (narrow, three buffers), 8 or 4 groups over 512 chunks (8 or 16 lanes,
+    // narrow), 1 group over 8192 chunks (64 lanes, wide, two words per cell)
     const int64_t p1 = 3 * boundary_buf_words(1);  // three boundary buffers of the packed pass
+    const int64_t p8 = 3 * boundary_buf_words(8);
     const int64_t p16 = 3 * boundary_buf_words(16);
     const int64_t p64 = (int64_t)((SW_MAX_SEQ_LEN + 7) / 8) * 1 * 16;
-    return std::max(p1, std::max(p16, p64));
+    return std::max(std::max(p1, p8), std::max(p16, p64));
 }
 
 __global__ void k_pack_header(PackedHeader* h, int64_t n)
@@ -1390,6 +1404,8 @@ static hipError_t launch_plain_r(const Args& a, int kind, int first, int count, 
         hipLaunchKernelGGL((k_plain<R, 64, true>), dim3(grid), dim3(kWave), lds, stream, a, first, count);
     else if (kind == 16)
         hipLaunchKernelGGL((k_plain<R, 16, false>), dim3(grid), dim3(kWave), lds, stream, a, first, count);
+    else if (kind == 8)
+        hipLaunchKernelGGL((k_plain<R, 8, false>), dim3(grid), dim3(kWave), lds, stream, a, first, count);
     else
         hipLaunchKernelGGL((k_plain<R, 1, false>), dim3(grid), dim3(kWave), lds, stream, a, first, count);
     return hipGetLastError();
@@ -1412,6 +1428,7 @@ static hipError_t set_attrs_r()
     hipError_t e = hipFuncSetAttribute((const void*)k_persistent<R>, at, bytes);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_plain<R, 1, false>, at, bytes);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_plain<R, 16, false>, at, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_plain<R, 8, false>, at, bytes);
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_plain<R, 64, true>, at, bytes);
     return e;
 }

@@ -48,7 +48,8 @@ constexpr int kMaxInterChunks = 128;   // ceil(inter_max_len / 8) <= this
 constexpr int kMaxInterLen = 1024;
 constexpr int kMaxP16Len = 4096;      // longest pair a 16-lane group may get; the packed
                                       // 16-bit pass also covers whole waves up to this
-constexpr int kDefaultGroup16Max = 4096;  // default group16_max_len
+constexpr int kDefaultGroup16Max = 2048;  // default group16_max_len (no 16-lane groups next to the 8-lane default)
+constexpr int kDefaultGroup8Max = 2048;   // default group8_max_len
 constexpr int kXbufBytes = 64 * 96;   // LDS exchange / staging buffer: 24 words per lane
 constexpr int kWideCostBins = 512;     // floor(16 * log2(m*n)) for long (wide) pairs
 constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
@@ -62,6 +63,7 @@ enum {
     kCntP64 = 1,    // pairs aligned by 64 lanes (longest)
     kCntP16 = 2,    // pairs aligned by 16 lanes
     kCntP1 = 3,     // pairs aligned by one lane
+    kCntP8 = 4,     // pairs aligned by 8 lanes
     kNumCounters = 16
 };
 enum { kErrRange = 1, kErrCode = 2, kErrInternal = 4 };
@@ -91,6 +93,7 @@ struct Args {
     int32_t rows_per_lane;
     int32_t inter_max_len;
     int32_t group16_max_len;   // longest pair of a 16-lane group (power of two)
+    int32_t group8_max_len;    // longest pair of an 8-lane group (power of two, <= group16_max_len)
     int32_t phase;             // 0: both passes per item; 1: forward pass only (writes score
                                // and end); 2: start pass only (reads them from out)
 };

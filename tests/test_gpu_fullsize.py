@@ -26,7 +26,7 @@ def sw():
     assert torch.cuda.is_available(), "no GPU"
     import paper_2303_01845_amd as lib
     lib.lib()
-    lib.set_tuning(16, 1024, -1, 4096)
+    lib.set_tuning(16, 1024, -1, 2048, 2048)
     return lib
 
 

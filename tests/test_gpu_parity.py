@@ -22,7 +22,7 @@ def sw():
     assert torch.cuda.is_available(), "no GPU"
     import paper_2303_01845_amd as lib
     lib.lib()
-    lib.set_tuning(16, 1024, -1, 4096)
+    lib.set_tuning(16, 1024, -1, 2048, 2048)
     return lib
 
 
@@ -147,17 +147,18 @@ def test_tuning_does_not_change_results(sw):
     ps = P.concat([P.config_small(), adversarial_set(3, 300, 1500)])
     ref = None
     try:
-        for R, im, bpc, g16 in [(16, 1024, 0, 2048), (8, 512, 0, 1024), (16, 64, 0, 64), (8, 256, 2, 4096),
-                                (16, 512, 1, 512), (8, 64, 3, 2048), (16, 768, 0, 4096)]:
-            sw.set_tuning(R, im, bpc, g16)
-            say("tuning R=%d inter_max=%d bpc=%d group16_max=%d" % (R, im, bpc, g16))
+        for R, im, bpc, g16, g8 in [(16, 1024, 0, 2048, 1024), (8, 512, 0, 1024, 64), (16, 64, 0, 64, 64),
+                                    (8, 256, 2, 4096, 512), (16, 512, 1, 512, 4096), (8, 64, 3, 2048, 128),
+                                    (16, 768, 0, 4096, 2048), (16, 64, -1, 4096, 256)]:
+            sw.set_tuning(R, im, bpc, g16, g8)
+            say("tuning R=%d inter_max=%d bpc=%d group16_max=%d group8_max=%d" % (R, im, bpc, g16, g8))
             got = gpu_align(sw, ps)
             if ref is None:
                 ref = got
                 assert_same(got, expect(ps), ps, "tuning reference")
             assert (got == ref).all(), (R, im, bpc)
     finally:
-        sw.set_tuning(16, 1024, -1, 4096)
+        sw.set_tuning(16, 1024, -1, 2048, 2048)
 
 
 def test_permuted_pairs(sw):

@@ -91,7 +91,8 @@ def test_tuning_argument_checks():
     L = sw.lib()
     assert L.sw_set_tuning(None) == sw.SW_EINVAL
     for bad in [(32, 0, 0, 0), (24, 0, 0, 0), (0, 32, 0, 0), (0, 4096, 0, 0), (0, 0, 9, 0), (8, 1024, 0, 0),
-                (0, 0, 0, 3000), (0, 0, 0, 8192), (0, 0, 0, 32), (0, 0, -2, 0)]:
+                (0, 0, 0, 3000), (0, 0, 0, 8192), (0, 0, 0, 32), (0, 0, -2, 0), (0, 0, 0, 0, 32),
+                (0, 0, 0, 0, 3000), (0, 0, 0, 0, 8192)]:
         assert L.sw_set_tuning(ctypes.byref(sw.Tuning(*bad))) == sw.SW_EINVAL
     assert L.sw_get_tuning(None) == sw.SW_EINVAL
     assert L.sw_matrix(1, None, None) == sw.SW_EINVAL
