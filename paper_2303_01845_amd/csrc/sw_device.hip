@@ -217,7 +217,8 @@ __device__ __forceinline__ void build_profile(uint8_t* prof, int lane, const uin
         sel[w][2] = s2;
     }
     uint8_t* base = prof + lane * prof_bytes(R);
-#pragma unroll 1
+    // four codes per trip, so that their table loads go out together
+#pragma unroll 4
     for (int c = 0; c < kNumSym; ++c) {
         const uint32_t* t = c_tables.tabb[c];
         const uint32_t t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3], t4 = t[4], t5 = t[5];
@@ -661,6 +662,36 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
     StripPick pick{0, -1, 0};
     auto chunk_x = [&](int c) __attribute__((always_inline)) -> int { return (c < 0 || 8 * c >= N) ? 0 : (REV ? -8 * c - 7 : 8 * c); };
 
+    // one lane per pair: the reference's first staged batch is the same for
+    // every strip, so it is loaded once and kept in registers
+    uint4 b0n0, b0n1, b0n2, b0h0, b0h1;
+    if constexpr (P == 1) {
+        const int lo0 = REV ? rv.off - 7 - 56 : rv.off;
+        const uint4* np = reinterpret_cast<const uint4*>(rv.nib + ((lo0 >> 3) & ~3));
+        const uint4* hp = reinterpret_cast<const uint4*>(rv.hib + ((lo0 >> 5) & ~3));
+        b0n0 = np[0];
+        b0n1 = np[1];
+        b0n2 = np[2];
+        b0h0 = hp[0];
+        b0h1 = hp[1];
+    }
+    // the query words of the next super-strip are loaded during the current
+    // one and decoded when it starts
+    uint32_t rq[2][4];
+    int rqq[2];
+    auto row_raw = [&](int r0) __attribute__((always_inline)) {
+        const int x = r0 >= M ? 0 : (REV ? -r0 - 15 : r0);
+#pragma unroll
+        for (int k8 = 0; k8 < 2; ++k8) {
+            const int q = qv.off + x + 8 * k8;
+            rq[k8][0] = qv.nib[q >> 3];
+            rq[k8][1] = qv.nib[(q >> 3) + 1];
+            rq[k8][2] = qv.hib[q >> 5];
+            rq[k8][3] = qv.hib[(q >> 5) + 1];
+            rqq[k8] = q;
+        }
+    };
+    row_raw(my_ss > 0 ? 16 * u : M);
 #pragma unroll 1
     for (int ss = 0; ss < wss; ++ss) {
         if (__ballot(!done && ss < my_ss) == 0) break;
@@ -668,7 +699,19 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         const int row0 = ss * 16 * P + 16 * u;
         {
             uint32_t qc[16];
-            row_codes<16, REV>(qv, gact ? row0 : M, M, qc);
+            const int r0 = gact ? row0 : M;
+#pragma unroll
+            for (int k8 = 0; k8 < 2; ++k8) {
+                const uint32_t nw = __builtin_amdgcn_alignbit(rq[k8][1], rq[k8][0], (uint32_t)(rqq[k8] & 7) * 4u);
+                const uint32_t hw = __builtin_amdgcn_alignbit(rq[k8][3], rq[k8][2], (uint32_t)(rqq[k8] & 31));
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int idx = 8 * k8 + k;
+                    const int r = REV ? (15 - idx) : idx;
+                    const uint32_t cd = ((nw >> (4 * k)) & 15u) | (((hw >> k) & 1u) << 4);
+                    qc[r] = (r0 + r < M) ? cd : (uint32_t)kPadCode;
+                }
+            }
             build_profile<16>(prof, lane, qc);
         }
         const bool read_top = ss > 0;
@@ -742,7 +785,11 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         };
         fetch(-u);
         if constexpr (P == 1) {
-            load_batch(0);
+            sn0 = b0n0;
+            sn1 = b0n1;
+            sn2 = b0n2;
+            sh0 = b0h0;
+            sh1 = b0h1;
             store_batch();
         }
         // Nothing in flight when the chunk loop starts: a load still pending
@@ -753,6 +800,7 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             load_batch(1);
             window_lds(0);
         }
+        row_raw(ss + 1 < my_ss ? row0 + 16 * P : M);
         // Iteration t: lane u on chunk c = t - u, A on columns 8c .. 8c+7,
         // B on 8c-1 .. 8c+6.  Each lane needs my_chunks + 1 chunk iterations
         // (the last one for B's final column); the very last iteration of the
