@@ -294,6 +294,28 @@ struct RowUnroll {
     }
 };
 
+// The same update keeping only a running maximum of H over the lane's rows
+// (the scan of the whole-wave path: one max per cell instead of a tracker).
+template <int R, int I>
+struct RowScan {
+    static __device__ __forceinline__ void run(int (&H)[R], int (&E)[R], int& mx, const uint32_t (&w)[R / 8], int& d,
+                                               int& F, uint32_t go, int ge)
+    {
+        int dn = 0;
+        if constexpr (I + 1 < R) dn = H[I] + (int)nib_score<R, I + 1>(w) - kScoreBias;
+        const int h = max(max(d, E[I]), F);
+        H[I] = h;
+        const int hg = (int)__builtin_elementwise_sub_sat((uint32_t)h, go);
+        E[I] = max(E[I] - ge, hg);
+        F = max(F - ge, hg);
+        opaque(E[I]);
+        opaque(F);
+        mx = max(mx, h);
+        d = dn;
+        if constexpr (I + 1 < R) RowScan<R, I + 1>::run(H, E, mx, w, d, F, go, ge);
+    }
+};
+
 // One column of a lane's R rows.  hdiag = H[row0-1][j-1]; F enters as
 // F[row0][j] and leaves as F[row0+R][j].
 template <int R, int TB>
@@ -303,6 +325,14 @@ __device__ __forceinline__ void column_step(int (&H)[R], int (&E)[R], uint32_t (
 {
     int d = hdiag + (int)nib_score<R, 0>(w) - kScoreBias;
     RowUnroll<R, 0>::template run<TB>(H, E, K, w, d, F, tag, go, ge);
+}
+
+template <int R>
+__device__ __forceinline__ void column_scan(int (&H)[R], int (&E)[R], int& mx, const uint32_t (&w)[R / 8], int hdiag,
+                                            int& F, uint32_t go, int ge)
+{
+    int d = hdiag + (int)nib_score<R, 0>(w) - kScoreBias;
+    RowScan<R, 0>::run(H, E, mx, w, d, F, go, ge);
 }
 
 // ------------------------------------------------------------------ wave helpers
@@ -383,10 +413,34 @@ __host__ __device__ constexpr int64_t boundary_buf_words(int P)
 // every lane (never written; one chunk of the widest boundary format).
 __device__ uint4 g_zero_row[4];
 
-template <int R, int P, bool REV, bool WIDE, bool ONE = false>
+// Words of one boundary-row buffer of the whole-wave path for n columns: one
+// group, H and F of every column, rounded to 256 bytes; its scan rotates
+// three of them, a pair too long for three in a slot runs the in-place sweep.
+__host__ __device__ constexpr int64_t wide_buf_words(int n) { return (((int64_t)(n + 7) / 8) * 16 + 63) & ~(int64_t)63; }
+constexpr int64_t kWideBufWords = wide_buf_words(SW_MAX_SEQ_LEN);
+
+// Result of a score-only pass: the super-strip whose int32 recompute gives the
+// exact cells, and the boundary buffer that holds its input row.
+struct StripPick {
+    int s;    // forward: best score (0 if none)
+    int ss;   // super-strip to recompute, -1 if none
+    int buf;  // boundary buffer holding its input row
+};
+
+// SCAN (whole-wave path): keep only the running maximum of each super-strip,
+// read and write separate boundary buffers (three of wide_buf_words(N) each,
+// rotated as in the packed pass) and report through *pick the super-strip to
+// recompute with ONE (same N, so the same buffers):
+// forward, the first one that reaches the best score, its input row kept; REV,
+// the first one whose maximum reaches `target`.  Padding cells stay below the
+// pair's maximum, so they cannot change either choice.
+template <int R, int P, bool REV, bool WIDE, bool ONE = false, bool SCAN = false>
 __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t* __restrict__ slot,
-                            int64_t Q0, int M, int64_t R0, int N, int target, int one_ss = -1, int one_buf = 0)
+                            int64_t Q0, int M, int64_t R0, int N, int target, int one_ss = -1, int one_buf = 0,
+                            StripPick* pick_out = nullptr)
 {
+    static_assert(!SCAN || (WIDE && !ONE), "the scan is the whole-wave path's score pass");
+    const int64_t BUFW = WIDE ? wide_buf_words(N) : boundary_buf_words(P);
     constexpr int TB = WIDE ? 12 : 16;  // tag bits of the per-row trackers
     constexpr int SW = WIDE ? 4 : 2;    // uint4 per boundary chunk of 8 columns
     constexpr int G = kWave / P;        // groups per wave
@@ -404,8 +458,9 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
     bool done = my_ss == 0 || (REV && target <= 0 && !ONE);
     const SeqView qv = seq_view(a.qblk, a.qhdr, Q0);
     const SeqView rv = seq_view(a.rblk, a.rhdr, R0);
-    uint4* slot4 = reinterpret_cast<uint4*>(slot + (ONE ? (int64_t)min(max(one_buf, 0), 2) * boundary_buf_words(P) : 0)) +
-                   SW * g;
+    uint4* slot4 = reinterpret_cast<uint4*>(slot + (ONE ? (int64_t)min(max(one_buf, 0), 2) * BUFW : 0)) + SW * g;
+    int bi = 0, bo = 1, bk = 2;  // SCAN: boundary buffers input, output, kept (uniform in the group)
+    StripPick pick{0, -1, 0};
     uint4* x_mine = xbuf + SW * lane;
     const uint4* x_up = xbuf + SW * (lane > 0 ? lane - 1 : 0);
 
@@ -429,6 +484,7 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
             K[r] = 0;
         }
         int hdiag = 0;
+        int mx = 0;  // SCAN: maximum of this lane's cells in the super-strip
         const bool read_top = sv > 0;                    // uniform within the group
         const bool write_next = !ONE && ss + 1 < my_ss;  // uniform within the group
 
@@ -465,7 +521,9 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
         // above, so padding stays below the pair's maximum), lanes u > 0
         // take the row from lane u - 1 instead, and the window words are
         // aligned where they are used.
-        const uint4* in4 = read_top ? slot4 : g_zero_row;
+        const uint4* rd4 = SCAN ? reinterpret_cast<const uint4*>(slot + bi * BUFW) + SW * g : slot4;
+        uint4* wr4 = SCAN ? reinterpret_cast<uint4*>(slot + bo * BUFW) + SW * g : slot4;
+        const uint4* in4 = read_top ? rd4 : g_zero_row;
         const int in_stride = read_top ? G * SW : 0;
         uint4 tc_n[SW];
         uint32_t na_n, nb_n, ha_n, hb_n;
@@ -540,7 +598,10 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
                         F = (int)(top[k] >> 16);
                         tag = (uint32_t)uni(0xFFFF - (8 * t + k));
                     }
-                    column_step<R, TB>(H, E, K, w, hdiag, F, tag, go, ge);
+                    if constexpr (SCAN)
+                        column_scan<R>(H, E, mx, w, hdiag, F, go, ge);
+                    else
+                        column_step<R, TB>(H, E, K, w, hdiag, F, tag, go, ge);
                     hdiag = htop;
                     if constexpr (WIDE) {
                         bot[2 * k] = (uint32_t)H[R - 1];
@@ -566,13 +627,41 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
             if (u == P - 1 && act && write_next) {
 #pragma unroll
                 for (int w = 0; w < SW; ++w)
-                    slot4[c * G * SW + w] = make_uint4(bot[4 * w], bot[4 * w + 1], bot[4 * w + 2], bot[4 * w + 3]);
+                    wr4[c * G * SW + w] = make_uint4(bot[4 * w], bot[4 * w + 1], bot[4 * w + 2], bot[4 * w + 3]);
             }
-            if constexpr (WIDE) {
+            if constexpr (WIDE && !SCAN) {
                 if ((t & 511) == 511) fold(8 * t + 7 - 4095);
             }
         }
         block_fence();
+        if constexpr (SCAN) {
+            int gm = mx;
+#pragma unroll
+            for (int o = 1; o < P; o <<= 1) gm = max(gm, __shfl_xor(gm, o, kWave));
+            if (gact) {
+                if (REV) {
+                    if (gm >= target) {
+                        pick = StripPick{gm, sv, bi};
+                        done = true;
+                    } else {
+                        const int tt = bi;
+                        bi = bo;
+                        bo = tt;
+                    }
+                } else if (gm > pick.s) {
+                    pick = StripPick{gm, sv, bi};
+                    const int tt = bk;
+                    bk = bi;
+                    bi = bo;
+                    bo = tt;
+                } else {
+                    const int tt = bi;
+                    bi = bo;
+                    bo = tt;
+                }
+            }
+            continue;
+        }
         if constexpr (WIDE) {
             fold((8 * T - 1) & ~4095);
         } else if (gact) {
@@ -590,6 +679,10 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
             const Best gb = group_best<P>(b);
             if (gact && gb.s >= target) done = true;
         }
+    }
+    if constexpr (SCAN) {
+        if (pick_out) *pick_out = pick;
+        return Best{pick.s, -1, -1};
     }
     return group_best<P>(b);
 }
@@ -625,12 +718,6 @@ __device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(
 // hand-over between lanes of one wave; the hardware keeps a wave's LDS
 // accesses in order).
 __device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
-
-struct StripPick {
-    int s;    // forward: best score (0 if none)
-    int ss;   // super-strip to recompute, -1 if none
-    int buf;  // boundary buffer holding its input row
-};
 
 template <int P, bool REV>
 __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, uint32_t* xw, uint32_t* __restrict__ slot,
@@ -1109,6 +1196,33 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
         }
         return;
     }
+    // whole wave: an int32 scan keeping only each super-strip's maximum, then
+    // the exact cells from one super-strip with trackers -- when three
+    // boundary buffers of the pair fit the slot (pairs up to ~32k columns);
+    // longer ones run the in-place sweep with trackers in every cell
+    if constexpr (WIDE) {
+        if (3 * wide_buf_words(n) <= a.slot_words) {
+            if (a.phase != 2) {
+                StripPick pf{0, -1, 0};
+                group_sweep<R, P, false, true, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, -1, 0, &pf);
+                f = group_sweep<R, P, false, true, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, pf.ss, pf.buf);
+                forward_done(pf.s);
+                if (a.phase == 1) return;
+            }
+            const bool hs = f.s > 0;
+            const int64_t qr = qoff + (hs ? f.i : 0), rr = roff + (hs ? f.j : 0);
+            const int mr = hs ? f.i + 1 : 0, nr = hs ? f.j + 1 : 0;
+            StripPick pr{0, -1, 0};
+            group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr);
+            const Best r = group_sweep<R, P, true, true, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s,
+                                                               hs ? pr.ss : -1, pr.buf);
+            if (pid >= 0 && u == 0) {
+                if (hs && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+                write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
+            }
+            return;
+        }
+    }
     if (a.phase != 2) {
         f = group_sweep<R, P, false, WIDE>(a, prof, xbuf, slot, qoff, m, roff, n, 0);
         forward_done(-1);
@@ -1386,11 +1500,12 @@ int64_t slot_words()
 {
     // [chunk][group][8 cells]: 64 groups of one lane over at most 128 chunks
     // (narrow, three buffers), 8 or 4 groups over 512 chunks (8 or 16 lanes,
-    // narrow), 1 group over 8192 chunks (64 lanes, wide, two words per cell)
+    // narrow), 1 group over 8192 chunks (64 lanes, wide, two words per cell;
+    // three buffers of the scan fit up to ~32k columns)
     const int64_t p1 = 3 * boundary_buf_words(1);  // three boundary buffers of the packed pass
     const int64_t p8 = 3 * boundary_buf_words(8);
     const int64_t p16 = 3 * boundary_buf_words(16);
-    const int64_t p64 = (int64_t)((SW_MAX_SEQ_LEN + 7) / 8) * 1 * 16;
+    const int64_t p64 = kWideBufWords;  // whole wave, longest pairs: one buffer, in place
     return std::max(std::max(p1, p8), std::max(p16, p64));
 }
 
