@@ -280,7 +280,7 @@ int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, Workspace** ou
     bool changed = false;
     if (!w.cell_count) {
         int rc;
-        if ((rc = grow(&w.cell_count, kNumCells)) || (rc = grow(&w.rank_start, kNumCells + 1)) ||
+        if ((rc = grow(&w.cell_count, (int64_t)kNumCells * kCellShards)) || (rc = grow(&w.rank_start, kNumCells + 1)) ||
             (rc = grow(&w.counters, kNumCounters)))
             return rc;
         HIP_TRY(hipHostMalloc((void**)&w.host_rank_start, sizeof(int32_t) * (kNumCells + 1)), "hipHostMalloc");

@@ -1413,7 +1413,7 @@ __global__ void k_fill(int32_t* p, int64_t n, int32_t v)
 
 __global__ void k_zero_cells(Args a)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNumCells; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNumCells * kCellShards; i += gridDim.x * blockDim.x)
         a.cell_count[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntHead] = 0;
 }
@@ -1424,13 +1424,14 @@ __global__ void k_prepare(Args a)
          k += (int64_t)gridDim.x * blockDim.x) {
         const int cell = a.phase == 2 ? classify_start(a, k) : classify(a, k);
         a.pair_cell[k] = cell;
-        if (cell >= 0) atomicAdd(&a.cell_count[cell], 1);
+        if (cell >= 0) atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1);
         else if (cell == -2) atomicOr((unsigned*)a.err, (unsigned)kErrRange);
     }
 }
 
-// Single block: exclusive scan of the cell counts in rank order; the counts
-// become scatter cursors; counters get the number of long and short pairs.
+// Single block: exclusive scan of the cell counts in rank order (a cell's
+// shards in shard order); the counts become scatter cursors; counters get the
+// number of pairs of each kind.
 __global__ __launch_bounds__(1024) void k_scan(Args a)
 {
     __shared__ int part[1024];
@@ -1440,12 +1441,28 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
     const int t = threadIdx.x;
     constexpr int per = (kNumCells + 1023) / 1024;
     const int lo = t * per, hi = min(kNumCells, lo + per);
+    static_assert(kCellShards == 16, "a cell's shards are read as four int4");
+    // this thread's cells first (independent loads), then their shards, a few
+    // cells at a time so that the loads overlap without spilling
+    int cells[per];
+#pragma unroll
+    for (int i = 0; i < per; ++i) cells[i] = lo + i < hi ? a.rank_cell[lo + i] : 0;
+    auto shard_sum = [&](int i) -> int {
+        const int4* q = reinterpret_cast<const int4*>(a.cell_count + cells[i] * kCellShards);
+        int c = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int4 x = q[v];
+            c += x.x + x.y + x.z + x.w;
+        }
+        return lo + i < hi ? c : 0;
+    };
     int sum = 0, c64 = 0, c16 = 0, c8 = 0;
-    for (int rk = lo; rk < hi; ++rk) {
-        const int cell = a.rank_cell[rk];
-        const int c = a.cell_count[cell];
+#pragma unroll 4
+    for (int i = 0; i < per; ++i) {
+        const int c = shard_sum(i);
         sum += c;
-        const int kind = cell_kind(cell, a.group8_max_len, a.group16_max_len);
+        const int kind = cell_kind(cells[i], a.group8_max_len, a.group16_max_len);
         if (kind == 64) c64 += c;
         else if (kind == 16) c16 += c;
         else if (kind == 8) c8 += c;
@@ -1468,12 +1485,22 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
         __syncthreads();
     }
     int run = part[t] - sum;  // exclusive prefix
-    for (int rk = lo; rk < hi; ++rk) {
-        const int cell = a.rank_cell[rk];
-        const int c = a.cell_count[cell];
-        a.rank_start[rk] = run;
-        a.cell_count[cell] = run;
-        run += c;
+#pragma unroll 2
+    for (int i = 0; i < per; ++i) {
+        if (lo + i >= hi) break;
+        a.rank_start[lo + i] = run;
+        int4* q = reinterpret_cast<int4*>(a.cell_count + cells[i] * kCellShards);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int4 x = q[v];
+            int4 y;
+            y.x = run;
+            y.y = run + x.x;
+            y.z = y.y + x.y;
+            y.w = y.z + x.z;
+            run = y.w + x.w;
+            q[v] = y;
+        }
     }
     if (t == 1023) {
         a.rank_start[kNumCells] = part[1023];
@@ -1489,7 +1516,7 @@ __global__ void k_scatter(Args a)
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int cell = a.pair_cell[k];
-        if (cell >= 0) a.perm[atomicAdd(&a.cell_count[cell], 1)] = (int32_t)k;
+        if (cell >= 0) a.perm[atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1)] = (int32_t)k;
     }
 }
 

@@ -56,6 +56,10 @@ constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
 constexpr int kInterCells = kMaxInterStrips * kMaxInterChunks;
 constexpr int kWideCells = kNumLenBuckets * kWideCostBins;
 constexpr int kNumCells = kInterCells + kWideCells;
+// Each cell's count and scatter cursor is split over this many counters
+// (pair index mod kCellShards), so that the atomics of a popular cell do not
+// all land on one address.
+constexpr int kCellShards = 16;
 
 // counters[] slots in the workspace
 enum {
@@ -82,7 +86,7 @@ struct Args {
     sw_result* out;
     int32_t* pair_cell;        // [n_pairs] work cell of each pair (-1 none, -2 invalid)
     int32_t* perm;             // [n_pairs] pair indices sorted by rank of their cell
-    int32_t* cell_count;       // [kNumCells] histogram, then scatter cursors
+    int32_t* cell_count;       // [kNumCells][kCellShards] histogram, then scatter cursors
     const int32_t* rank_cell;  // [kNumCells] cell at each rank
     int32_t* rank_start;       // [kNumCells + 1] first perm position of each rank
     int32_t* counters;         // [kNumCounters]
