@@ -69,8 +69,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(pairs are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(pairs are independent, so the work would shard by pairs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
