@@ -160,6 +160,14 @@ SW_API int sw_check(void* stream);
 SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
 
 /*
+ * The same read, split by pass: *forward_ms sums the forward launches of
+ * persistent calls (and the whole launch series of SW_PLAIN calls, which run
+ * both passes together), *start_ms the start-pass launches.  Synchronises
+ * `stream`, forgets the timed calls.  Errors: SW_EINVAL, SW_EDEVICE.
+ */
+SW_API int sw_timing_read_passes(void* stream, double* forward_ms, double* start_ms, int64_t* calls);
+
+/*
  * Kernel shape used by later calls on the current device.  rows_per_lane is
  * the number of query rows each lane keeps in registers (8 or 16);
  * inter_max_len is the longest pair (max of both lengths, 64..1024, at most

@@ -33,7 +33,7 @@ TIMED = 8
 
 # every function the C header declares
 EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_check", "sw_timing_read",
-           "sw_set_tuning",
+           "sw_timing_read_passes", "sw_set_tuning",
            "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
            "sw_server_submit", "sw_server_poll", "sw_server_wait", "sw_server_stats",
            "sw_server_request_bytes", "sw_server_destroy")
@@ -85,6 +85,8 @@ def lib():
         L.sw_check.argtypes = [ctypes.c_void_p]
         L.sw_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64)]
+        L.sw_timing_read_passes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.sw_server_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.POINTER(Scoring), ctypes.c_size_t, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_void_p)]
@@ -194,6 +196,15 @@ def timing_read(stream=None):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib().sw_timing_read(_stream_ptr(stream), ctypes.byref(ms), ctypes.byref(n)), "sw_timing_read")
     return ms.value, n.value
+
+
+def timing_read_passes(stream=None):
+    """(forward ms, start-pass ms, calls) over the SW_TIMED calls on `stream`
+    since the previous read (SW_PLAIN calls count as forward); synchronises."""
+    f, s, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check(lib().sw_timing_read_passes(_stream_ptr(stream), ctypes.byref(f), ctypes.byref(s), ctypes.byref(n)),
+           "sw_timing_read_passes")
+    return f.value, s.value, n.value
 
 
 def set_tuning(rows_per_lane: int = 0, inter_max_len: int = 0, blocks_per_cu: int = 0,

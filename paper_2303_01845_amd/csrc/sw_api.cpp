@@ -166,6 +166,7 @@ struct Workspace {
     // SW_TIMED: event pairs recorded and not yet read (one per persistent
     // launch), the number of calls they belong to, and a pool to reuse
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, event_pool;
+    std::vector<int> timed_pass;  // per timed pair: 0 forward (plain: both passes), 1 start
     int64_t timed_calls = 0;
 
     void drop_graphs()
@@ -477,7 +478,10 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
         for (int k = 0; k < 2; ++k) {
             auto it = std::find(w.event_pool.begin(), w.event_pool.end(), ev[k]);
             if (it != w.event_pool.end()) w.event_pool.erase(it);
-            if (k < n_timed) w.timed.push_back(ev[k]);
+            if (k < n_timed) {
+                w.timed.push_back(ev[k]);
+                w.timed_pass.push_back(k);
+            }
             else w.event_pool.push_back(ev[k]);
         }
         if (n_timed > 0) ++w.timed_calls;
@@ -570,32 +574,43 @@ int sw_check(void* stream)
     return read_and_clear_errors(*d, (hipStream_t)stream);
 }
 
-int sw_timing_read(void* stream_, double* kernel_ms, int64_t* calls)
+int sw_timing_read_passes(void* stream_, double* forward_ms, double* start_ms, int64_t* calls)
 {
-    if (!kernel_ms || !calls) return SW_EINVAL;
+    if (!forward_ms || !start_ms || !calls) return SW_EINVAL;
     hipStream_t stream = (hipStream_t)stream_;
     std::lock_guard<std::mutex> lock(g_mutex);
     Device* d = nullptr;
     int rc = get_device(&d);
     if (rc) return rc;
-    *kernel_ms = 0.0;
+    *forward_ms = *start_ms = 0.0;
     *calls = 0;
     auto it = d->ws.find(stream);
     if (it == d->ws.end()) return SW_OK;
     Workspace& w = *it->second;
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    double total = 0.0;
-    for (auto& e : w.timed) {
+    double sum[2] = {0.0, 0.0};
+    for (size_t k = 0; k < w.timed.size(); ++k) {
         float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
-        total += ms;
+        HIP_TRY(hipEventElapsedTime(&ms, w.timed[k].first, w.timed[k].second), "hipEventElapsedTime");
+        sum[w.timed_pass[k] == 1 ? 1 : 0] += ms;
     }
-    *kernel_ms = total;
+    *forward_ms = sum[0];
+    *start_ms = sum[1];
     *calls = w.timed_calls;
     for (auto& e : w.timed) w.event_pool.push_back(e);
     w.timed.clear();
+    w.timed_pass.clear();
     w.timed_calls = 0;
     return SW_OK;
+}
+
+int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls)
+{
+    if (!kernel_ms || !calls) return SW_EINVAL;
+    double f = 0.0, s = 0.0;
+    const int rc = sw_timing_read_passes(stream, &f, &s, calls);
+    *kernel_ms = f + s;
+    return rc;
 }
 
 int sw_set_tuning(const sw_tuning* t)

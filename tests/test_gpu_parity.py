@@ -254,7 +254,12 @@ def test_timed_calls(sw):
             torch.cuda.synchronize()
             outer += e0.elapsed_time(e1)
             assert_same(got, exp, ps, "timed " + label)
-        ms, calls = sw.timing_read(stream)
+        if flags == sw.PLAIN:
+            ms, calls = sw.timing_read(stream)
+        else:
+            fwd, start, calls = sw.timing_read_passes(stream)
+            assert fwd > 0.0 and start > 0.0, (label, fwd, start)
+            ms = fwd + start
         assert calls == 2 and ms > 0.0, (label, ms, calls)
         # the library's events sit inside the calls: their sum cannot exceed
         # the time between events recorded around the calls
