@@ -1292,13 +1292,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
 __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, uint32_t* __restrict__ blk,
                        int64_t n_hib_words, int32_t* err)
 {
+    // the letter -> code table in LDS: each residue is one LDS byte read
+    // instead of a divergent load from constant memory
+    __shared__ uint8_t tab[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) tab[i] = c_tables.ascii[i];
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_hib_words) return;
     const int64_t p0 = 32 * t - kGuardRes;
     uint32_t nib[4] = {0, 0, 0, 0}, hib = 0;
     bool bad = false;
     auto put = [&](int k, uint32_t letter) {
-        uint32_t c = c_tables.ascii[letter];
+        uint32_t c = tab[letter];
         if (c == 0xFFu) {
             c = kPadCode;
             bad = true;
