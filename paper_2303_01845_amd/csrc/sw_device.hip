@@ -19,8 +19,8 @@
 // recurrence: by induction E_sat = max(E, 0), and H only uses max(0, E).
 //
 // Work decomposition.  Pairs up to 1024 residues get one lane each, longer
-// ones up to 2048 a group of 8 lanes, up to 4096 a group of 16 lanes, longer
-// still a whole wave (the limits are tunable).  A lane
+// ones up to 2048 a group of 8 lanes, longer still a whole wave (the limits
+// are tunable; a middle tier of 16-lane groups is off by default).  A lane
 // keeps R query rows in registers and sweeps the reference in chunks of 8
 // columns; a group of P lanes covers a super-strip of P R rows as a
 // wavefront, and super-strips hand their bottom row to the next one through a
@@ -1239,7 +1239,8 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
 
 // ------------------------------------------------------------------ kernels
 // Work items, in queue order: single pairs over 64 lanes (longest first),
-// groups of 4 pairs over 16 lanes each, groups of 64 pairs one per lane.
+// groups of 4 pairs over 16 lanes each, of 8 pairs over 8 lanes each, of 64
+// pairs one per lane.
 template <int R>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_persistent(Args a)
 {
