@@ -7,7 +7,9 @@ its own C source (``sw_oracle.c``), its own substitution table parsed from
 ``blosum62.txt``, its own ASCII encoder.
 
 The recurrence, the gap model and the tie rule are stated in the header of
-``sw_oracle.c`` (the paper, section "Load balancing techniques": the aligner
+``sw_oracle.c``; candidate discovery (distinct shared k-mers, the overlap
+product of the k-mer matrix with itself) in the header of
+``discover_oracle.c`` (the paper, section "Load balancing techniques": the aligner
 fills the entire dynamic-programming matrix; "Performance results", program
 parameter table: affine gap open / extension penalties, integer scores).
 """
@@ -23,6 +25,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sw_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+DISCOVER_SRC = os.path.join(HERE, "discover_oracle.c")
+DISCOVER_LIB = os.path.join(HERE, "liboracle_discover.so")
 MATRIX_TXT = os.path.join(HERE, "blosum62.txt")
 
 
@@ -42,8 +46,9 @@ def compile_oracle(src: str, out: str) -> str:
 
 
 def build(force: bool = True) -> str:
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        compile_oracle(SRC, LIB)
+    for src, lib in ((SRC, LIB), (DISCOVER_SRC, DISCOVER_LIB)):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            compile_oracle(src, lib)
     return LIB
 
 
@@ -173,3 +178,82 @@ def batch_ascii(ascii: np.ndarray, offsets, pairs, go: int = 11, ge: int = 1,
     align.  Residues that are not matrix symbols raise."""
     codes = default().encode(np.ascontiguousarray(ascii, dtype=np.uint8).tobytes())
     return default().batch(codes, offsets, pairs, go, ge, threads)
+
+
+class DiscoverLib:
+    """ctypes view of one compiled candidate-discovery oracle (the default
+    build, or a deliberately altered copy used to show that its pins catch
+    mistakes)."""
+
+    def __init__(self, path: str):
+        L = ctypes.CDLL(path)
+        L.oracle_discover.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_distinct_kmers.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_int32, ctypes.c_void_p]
+        self.L = L
+
+    def discover_codes(self, q_codes, q_offs, r_codes, r_offs, k: int = 6, min_shared: int = 2,
+                       mode: int = 0):
+        """(query, reference, shared) int32 arrays of every pair with at least
+        ``min_shared`` distinct common k-mers, in (query, reference) order.
+        mode 0: all pairs; 1: query < reference; 2: the index-parity rule."""
+        qc = np.ascontiguousarray(q_codes, dtype=np.int8)
+        rc_ = np.ascontiguousarray(r_codes, dtype=np.int8)
+        qo = np.ascontiguousarray(q_offs, dtype=np.int64)
+        ro = np.ascontiguousarray(r_offs, dtype=np.int64)
+        found = ctypes.c_int64(0)
+        args = (qc.ctypes.data, qo.ctypes.data, len(qo) - 1, rc_.ctypes.data, ro.ctypes.data,
+                len(ro) - 1, k, min_shared, mode)
+        rc = self.L.oracle_discover(*args, 0, None, None, None, ctypes.byref(found))
+        if rc != 0:
+            raise ValueError("oracle_discover failed (rc=%d)" % rc)
+        n = found.value
+        out = np.zeros((3, max(n, 1)), dtype=np.int32)
+        rc = self.L.oracle_discover(*args, n, out[0].ctypes.data, out[1].ctypes.data,
+                                    out[2].ctypes.data, ctypes.byref(found))
+        if rc != 0 or found.value != n:
+            raise ValueError("oracle_discover failed (rc=%d)" % rc)
+        return out[0, :n].copy(), out[1, :n].copy(), out[2, :n].copy()
+
+    def distinct_kmers_codes(self, codes, offs, k: int = 6) -> np.ndarray:
+        c = np.ascontiguousarray(codes, dtype=np.int8)
+        o = np.ascontiguousarray(offs, dtype=np.int64)
+        out = np.zeros(max(len(o) - 1, 1), dtype=np.int64)
+        rc = self.L.oracle_distinct_kmers(c.ctypes.data, o.ctypes.data, len(o) - 1, k,
+                                          out.ctypes.data)
+        if rc != 0:
+            raise ValueError("oracle_distinct_kmers failed (rc=%d)" % rc)
+        return out[:len(o) - 1]
+
+
+_discover = None
+
+
+def discover_lib() -> DiscoverLib:
+    global _discover
+    with _lock:
+        if _discover is None:
+            build(force=False)
+            _discover = DiscoverLib(DISCOVER_LIB)
+    return _discover
+
+
+def _ascii_codes(ascii) -> np.ndarray:
+    if isinstance(ascii, (bytes, bytearray, str)):
+        return default().encode(ascii)
+    return default().encode(np.ascontiguousarray(ascii, dtype=np.uint8).tobytes())
+
+
+def discover(q_ascii, q_offs, r_ascii, r_offs, k: int = 6, min_shared: int = 2, mode: int = 0):
+    """Candidate pairs of two ASCII sequence sets (see ``DiscoverLib.discover_codes``)."""
+    return discover_lib().discover_codes(_ascii_codes(q_ascii), q_offs, _ascii_codes(r_ascii),
+                                         r_offs, k, min_shared, mode)
+
+
+def distinct_kmers(ascii, offs, k: int = 6) -> np.ndarray:
+    """Number of distinct k-mers of every sequence."""
+    return discover_lib().distinct_kmers_codes(_ascii_codes(ascii), offs, k)
