@@ -235,9 +235,64 @@ def main():
         "paper_context": "paper: 690.6 M alignments/s and 176.3 TCUPS peak on 20,184 V100 GPUs "
                          "(whole application, multi-node; not a 1-GPU target)",
     }
+    if args.workload == "block-50kx50k":
+        res["discovery"] = discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args)
+        res["discovery"]["pipeline_gcups"] = round(
+            cells / ((res["discovery"]["ms"] + ms_per_step) * 1e-3) / 1e9, 2)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args):
+    """Candidate discovery (sw_discover, k = 6, >= 2 shared) of the block
+    workload's 50k queries against its 50k references, on the resident packed
+    set: wall time per call (the call is synchronous), and the candidate set
+    checked against the one the workload generator built."""
+    import oracle
+    nq = (ps.n_seqs + 1) // 2
+    qo, ro = offs_d[:nq + 1], offs_d[nq:]
+    cap = ps.n_pairs + 1024
+    pairs = torch.empty((cap, 2), dtype=torch.int32, device=offs_d.device)
+    shared = torch.empty(cap, dtype=torch.int32, device=offs_d.device)
+    L = sw.lib()
+    import ctypes
+    found = ctypes.c_int64()
+    call_args = (ctypes.c_void_p(packed_d.data_ptr()), ctypes.c_void_p(qo.data_ptr()), nq,
+                 ctypes.c_void_p(packed_d.data_ptr()), ctypes.c_void_p(ro.data_ptr()), ps.n_seqs - nq, 6, 2,
+                 sw.DISCOVER_ALL, ctypes.c_void_p(pairs.data_ptr()), ctypes.c_void_p(shared.data_ptr()), cap,
+                 ctypes.byref(found), ctypes.c_void_p(stream.cuda_stream))
+    for _ in range(2):
+        rc = L.sw_discover(*call_args)
+        if rc:
+            raise sw.SwError(rc, "sw_discover")
+    steps = max(3, args.steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        L.sw_discover(*call_args)
+    wall = (time.perf_counter() - t) / steps
+    n = found.value
+    got = pairs[:n].cpu().numpy().astype(np.int64)
+    got = got[np.lexsort((got[:, 1], got[:, 0]))]
+    gen = ps.pairs.astype(np.int64)
+    gen = gen[np.lexsort((gen[:, 1], gen[:, 0]))]
+    same = bool(len(got) == len(gen) and np.array_equal(got[:, 0], gen[:, 0]) and
+                np.array_equal(got[:, 1] + nq, gen[:, 1]))
+    lens = np.diff(ps.offsets)
+    windows = int(np.maximum(lens - 5, 0).sum())
+    cut = int(ps.offsets[nq])
+    t = time.perf_counter()
+    oq, _, _ = oracle.discover(ps.ascii[:cut], ps.offsets[:nq + 1], ps.ascii[cut:], ps.offsets[nq:] - cut, 6, 2)
+    cpu_s = time.perf_counter() - t
+    log("discovery: %.3f ms per call, %d candidates (generator set %s), oracle %.2f s (1 core)" % (
+        wall * 1e3, n, "equal" if same else "DIFFERENT", cpu_s))
+    return {"ms": round(wall * 1e3, 3), "candidates": n, "kmer_windows": windows,
+            "candidates_per_s": round(n / wall, 1), "windows_per_s": round(windows / wall, 1),
+            "steps": steps, "k": 6, "min_shared": 2,
+            "equals_generator_set": same,
+            "oracle_cpu": {"seconds": round(cpu_s, 3), "cores": 1, "kind": "oracle",
+                           "candidates": int(len(oq))}}
 
 
 def serve_bench(args):

@@ -215,6 +215,57 @@ SW_API int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64
  */
 SW_API int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters);
 
+/* ---------------------------------------------------------- candidate discovery
+ * Which pairs to align: every (query, reference) pair whose sequences have at
+ * least min_shared DISTINCT k-mers (runs of k consecutive residues) in
+ * common.  This is the overlap product of the paper's sequence-by-k-mer
+ * matrix with itself (section "Protein similarity search pipeline": the
+ * product counts common k-mers; section "Similarity search at scale":
+ * k = 6, threshold 2).  A sequence that repeats a k-mer holds it once; a
+ * sequence shorter than k has none.
+ *
+ * Inputs are two sets packed by sw_pack (they may be the same buffer and
+ * offsets: a self search), with int64 device offsets as for sw_align_sets.
+ * mode selects the pairs of a self search (section "Load balancing
+ * techniques": the overlap matrix is symmetric, one alignment per unordered
+ * pair suffices):
+ *   SW_DISCOVER_ALL     every (q, r) pair, the diagonal of a self search
+ *                       included;
+ *   SW_DISCOVER_UPPER   q < r only (the triangularity scheme);
+ *   SW_DISCOVER_PARITY  the index-based scheme: q > r with equal index
+ *                       parities, or q < r with different ones.
+ * The two self-search modes need n_q == n_r and keep exactly one of every
+ * unordered pair {i, j}, i != j.
+ *
+ * Output: pairs_out_dev int32[2 * out_cap] receives (query, reference) index
+ * pairs -- the layout sw_align_sets takes -- and shared_out_dev int32[out_cap]
+ * (may be NULL) the count of distinct shared k-mers of each.  The ORDER of the
+ * pairs is unspecified (it varies from call to call); the set is exact.
+ * *n_found (host) receives the total number of qualifying pairs; when it
+ * exceeds out_cap only out_cap of them are written and the call returns
+ * SW_ENOMEM, so a caller may size its buffers with out_cap = 0 first.
+ *
+ * The call is synchronous with respect to the host (it reads table sizes
+ * back between its launches) and enqueues everything on `stream`.  Its
+ * workspace (hash tables of twice the number of k-mer windows and of twice
+ * the number of k-mer matches, two int32 arrays of 24^k entries) grows to the
+ * largest call seen on the stream and is kept for reuse.
+ *
+ * Errors: SW_EINVAL (null pointer, k outside 1..6, min_shared < 1, unknown
+ * mode, a self-search mode with n_q != n_r), SW_ERANGE (offsets not
+ * increasing or beyond the packed buffer, 2^31 or more k-mer windows in the
+ * reference set), SW_ECODE (a residue that is not a symbol), SW_ENOMEM
+ * (device memory, or out_cap too small), SW_EDEVICE.
+ */
+#define SW_DISCOVER_ALL 0
+#define SW_DISCOVER_UPPER 1
+#define SW_DISCOVER_PARITY 2
+
+SW_API int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                       const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
+                       int32_t k, int32_t min_shared, int32_t mode, int32_t* pairs_out_dev,
+                       int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching against a reference set resident in HBM.  The server
  * keeps `max_slots` HIP streams, each with its own alignment workspace, and an

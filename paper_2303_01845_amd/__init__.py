@@ -36,7 +36,11 @@ EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_
            "sw_timing_read_passes", "sw_set_tuning",
            "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
            "sw_server_submit", "sw_server_poll", "sw_server_wait", "sw_server_stats",
-           "sw_server_request_bytes", "sw_server_destroy")
+           "sw_server_request_bytes", "sw_server_destroy", "sw_discover")
+
+DISCOVER_ALL = 0
+DISCOVER_UPPER = 1
+DISCOVER_PARITY = 2
 
 
 class SwError(RuntimeError):
@@ -106,6 +110,11 @@ def lib():
                                   ctypes.c_int64, ctypes.POINTER(Scoring), ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float)]
         L.sw_matrix.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_char_p]
+        L.sw_discover.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.c_void_p]
         L.sw_strerror.argtypes = [ctypes.c_int]
         L.sw_strerror.restype = ctypes.c_char_p
         L.sw_last_device_error.restype = ctypes.c_char_p
@@ -248,6 +257,34 @@ def matrix():
     letters = ctypes.create_string_buffer(25)
     _check(lib().sw_matrix(0, scores.ctypes.data, letters), "sw_matrix")
     return scores.reshape(24, 24), letters.value.decode()
+
+
+def discover(q_packed, q_offsets, r_packed, r_offsets, k: int = 6, min_shared: int = 2,
+             mode: int = DISCOVER_ALL, capacity: int | None = None, stream=None):
+    """Candidate pairs with at least ``min_shared`` distinct common k-mers
+    (sw_discover).  Returns (pairs int32 [n, 2], shared int32 [n]) on the GPU,
+    in unspecified order.  Without ``capacity`` the library is asked for the
+    count first; with it, a too-small capacity raises SW_ENOMEM."""
+    import torch
+    assert q_offsets.dtype == torch.int64 and r_offsets.dtype == torch.int64
+    L = lib()
+    st = _stream_ptr(stream)
+    dev = q_offsets.device
+    args = (ctypes.c_void_p(q_packed.data_ptr()), ctypes.c_void_p(q_offsets.data_ptr()),
+            int(q_offsets.numel()) - 1, ctypes.c_void_p(r_packed.data_ptr()),
+            ctypes.c_void_p(r_offsets.data_ptr()), int(r_offsets.numel()) - 1, int(k), int(min_shared), int(mode))
+    found = ctypes.c_int64()
+    if capacity is None:
+        status = L.sw_discover(*args, None, None, 0, ctypes.byref(found), st)
+        if status not in (SW_OK, SW_ENOMEM):
+            _check(status, "sw_discover")
+        capacity = found.value
+    pairs = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=dev)
+    shared = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    _check(L.sw_discover(*args, ctypes.c_void_p(pairs.data_ptr()), ctypes.c_void_p(shared.data_ptr()),
+                         int(capacity), ctypes.byref(found), st), "sw_discover")
+    n = found.value
+    return pairs[:n], shared[:n]
 
 
 class Batch:

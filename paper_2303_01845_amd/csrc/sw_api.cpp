@@ -10,6 +10,7 @@
 #include <tuple>
 #include <vector>
 
+#include "kmer_internal.h"
 #include "sw_internal.h"
 
 using namespace swk;
@@ -136,6 +137,41 @@ struct GraphKey {
     }
 };
 
+// Tables of candidate discovery on one stream; each grows to the largest
+// call seen and is kept.
+struct DiscoverSpace {
+    uint64_t* set_r = nullptr;  // (reference << 32 | k-mer) hash set
+    int64_t set_r_cap = 0;
+    uint64_t* set_q = nullptr;  // the same for the query set (unused in a self search)
+    int64_t set_q_cap = 0;
+    int32_t* kcount = nullptr;  // [24^k] references per k-mer, then fill cursors
+    int32_t* kstart = nullptr;  // [24^k + 1] first list entry of each k-mer
+    int64_t kspace = 0;
+    int64_t* tile_sums = nullptr;
+    int64_t tiles = 0;
+    int32_t* rlist = nullptr;   // references grouped by k-mer
+    int64_t rlist_cap = 0;
+    uint64_t* pkeys = nullptr;  // (query << 32 | reference) hash table
+    int32_t* pcount = nullptr;  // its shared-k-mer counters
+    int64_t pcap = 0;
+    uint64_t* counters = nullptr;
+    uint64_t* host = nullptr;   // pinned copy of counters
+
+    ~DiscoverSpace()
+    {
+        (void)hipFree(set_r);
+        (void)hipFree(set_q);
+        (void)hipFree(kcount);
+        (void)hipFree(kstart);
+        (void)hipFree(tile_sums);
+        (void)hipFree(rlist);
+        (void)hipFree(pkeys);
+        (void)hipFree(pcount);
+        (void)hipFree(counters);
+        if (host) (void)hipHostFree(host);
+    }
+};
+
 // Scratch and queues of one stream.  Kernels of two calls on the same stream
 // run in order, so they can share it; calls on different streams get their
 // own workspace.
@@ -168,6 +204,7 @@ struct Workspace {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, event_pool;
     std::vector<int> timed_pass;  // per timed pair: 0 forward (plain: both passes), 1 start
     int64_t timed_calls = 0;
+    std::unique_ptr<DiscoverSpace> discover;
 
     void drop_graphs()
     {
@@ -361,6 +398,29 @@ int read_and_clear_errors(Device& d, hipStream_t stream)
     if (bits) HIP_TRY(hipMemset(d.err, 0, sizeof(int32_t)), "clear errors");
     if (bits & kErrInternal) {
         std::snprintf(g_last_error, sizeof(g_last_error), "internal consistency check failed on the device");
+        return SW_EDEVICE;
+    }
+    if (bits & kErrRange) return SW_ERANGE;
+    if (bits & kErrCode) return SW_ECODE;
+    return SW_OK;
+}
+
+int64_t pow2_at_least(int64_t v)
+{
+    int64_t c = 256;
+    while (c < v) c <<= 1;
+    return c;
+}
+
+// Copy the discovery counters to the host and map their error bits.
+int read_counters(DiscoverSpace& x, hipStream_t stream)
+{
+    HIP_TRY(hipMemcpyAsync(x.host, x.counters, sizeof(uint64_t) * kKmNumCounters, hipMemcpyDeviceToHost, stream),
+            "read counters");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const uint64_t bits = x.host[kKmErr];
+    if (bits & kErrInternal) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "discovery: a hash table had no free slot");
         return SW_EDEVICE;
     }
     if (bits & kErrRange) return SW_ERANGE;
@@ -563,6 +623,116 @@ int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n
 {
     return sw_align_sets(packed_dev, offsets_dev, n_seqs, packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs,
                          scoring, out_dev, stream, flags);
+}
+
+int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                const int64_t* r_offsets_dev, int64_t n_r, int32_t k, int32_t min_shared, int32_t mode,
+                int32_t* pairs_out_dev, int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found, void* stream_)
+{
+    if (!n_found) return SW_EINVAL;
+    *n_found = 0;
+    if (k < 1 || k > kKmerMaxK || min_shared < 1 || mode < SW_DISCOVER_ALL || mode > SW_DISCOVER_PARITY ||
+        n_q < 0 || n_r < 0 || out_cap < 0)
+        return SW_EINVAL;
+    if (mode != SW_DISCOVER_ALL && n_q != n_r) return SW_EINVAL;
+    if (out_cap > 0 && !pairs_out_dev) return SW_EINVAL;
+    if (n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF) return SW_ERANGE;
+    if (n_q == 0 || n_r == 0) return SW_OK;
+    if (!q_packed_dev || !q_offsets_dev || !r_packed_dev || !r_offsets_dev) return SW_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(q_packed_dev) | reinterpret_cast<uintptr_t>(r_packed_dev)) & 15u)
+        return SW_EINVAL;
+    hipStream_t stream = (hipStream_t)stream_;
+
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* dp = nullptr;
+    int rc = get_device(&dp);
+    if (rc) return rc;
+    Workspace* wp = nullptr;
+    if ((rc = get_workspace(*dp, stream, 0, &wp))) return rc;
+    if (!wp->discover) wp->discover.reset(new DiscoverSpace());
+    DiscoverSpace& x = *wp->discover;
+    if (!x.counters) {
+        if ((rc = grow(&x.counters, kKmNumCounters))) return rc;
+        HIP_TRY(hipHostMalloc((void**)&x.host, sizeof(uint64_t) * kKmNumCounters), "hipHostMalloc");
+    }
+    auto side = [](const void* packed, const int64_t* offs, int64_t n) {
+        KmerSide s;
+        s.blk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(packed) + kHeaderBytes);
+        s.hdr = reinterpret_cast<const PackedHeader*>(packed);
+        s.offs = offs;
+        s.n = n;
+        return s;
+    };
+    const KmerSide R = side(r_packed_dev, r_offsets_dev, n_r);
+    const KmerSide Q = side(q_packed_dev, q_offsets_dev, n_q);
+    const bool same = q_packed_dev == r_packed_dev && q_offsets_dev == r_offsets_dev && n_q == n_r;
+
+    // 1. windows per set, offsets checked before any kernel reads residues
+    HIP_TRY(hipMemsetAsync(x.counters, 0, sizeof(uint64_t) * kKmNumCounters, stream), "clear counters");
+    HIP_TRY(launch_kmer_positions(R, k, kKmPosR, x.counters, stream), "discover launch");
+    if (!same) HIP_TRY(launch_kmer_positions(Q, k, kKmPosQ, x.counters, stream), "discover launch");
+    if ((rc = read_counters(x, stream))) return rc;
+    const int64_t pos_r = (int64_t)x.host[kKmPosR];
+    const int64_t pos_q = same ? pos_r : (int64_t)x.host[kKmPosQ];
+    if (pos_r >= (int64_t)0x7FFFFFFF) return SW_ERANGE;
+
+    // 2. distinct (sequence, k-mer) entries; the reference side counts them per k-mer
+    const int64_t cap_r = pow2_at_least(2 * pos_r);
+    if (cap_r > x.set_r_cap) {
+        if ((rc = grow(&x.set_r, cap_r))) return x.set_r_cap = 0, rc;
+        x.set_r_cap = cap_r;
+    }
+    const int64_t cap_q = same ? cap_r : pow2_at_least(2 * pos_q);
+    if (!same && cap_q > x.set_q_cap) {
+        if ((rc = grow(&x.set_q, cap_q))) return x.set_q_cap = 0, rc;
+        x.set_q_cap = cap_q;
+    }
+    const int64_t kspace = kmer_space(k);
+    if (kspace > x.kspace) {
+        if ((rc = grow(&x.kcount, kspace)) || (rc = grow(&x.kstart, kspace + 1))) return x.kspace = 0, rc;
+        x.kspace = kspace;
+    }
+    const int64_t tiles = kmer_scan_tiles(kspace);
+    if (tiles > x.tiles) {
+        if ((rc = grow(&x.tile_sums, tiles))) return x.tiles = 0, rc;
+        x.tiles = tiles;
+    }
+    if (pos_r > x.rlist_cap) {
+        if ((rc = grow(&x.rlist, pos_r))) return x.rlist_cap = 0, rc;
+        x.rlist_cap = pos_r;
+    }
+    uint64_t* set_q = same ? x.set_r : x.set_q;
+    HIP_TRY(hipMemsetAsync(x.set_r, 0xFF, sizeof(uint64_t) * cap_r, stream), "clear table");
+    if (!same) HIP_TRY(hipMemsetAsync(set_q, 0xFF, sizeof(uint64_t) * cap_q, stream), "clear table");
+    HIP_TRY(hipMemsetAsync(x.kcount, 0, sizeof(int32_t) * kspace, stream), "clear counts");
+    HIP_TRY(launch_kmer_insert(R, k, x.set_r, cap_r, x.kcount, x.counters, stream), "discover launch");
+    if (!same) HIP_TRY(launch_kmer_insert(Q, k, set_q, cap_q, nullptr, x.counters, stream), "discover launch");
+
+    // 3. the reference lists of every k-mer
+    HIP_TRY(launch_kmer_scan(x.kcount, x.kstart, kspace, x.tile_sums, stream), "discover launch");
+    HIP_TRY(launch_kmer_scatter(x.set_r, cap_r, x.kstart, x.kcount, x.rlist, stream), "discover launch");
+
+    // 4. size the pair table by the number of k-mer matches, then count
+    HIP_TRY(launch_kmer_products(set_q, cap_q, x.kstart, x.counters, stream), "discover launch");
+    if ((rc = read_counters(x, stream))) return rc;
+    const int64_t products = (int64_t)x.host[kKmProducts];
+    const int64_t pcap = pow2_at_least(2 * products);
+    if (pcap > x.pcap) {
+        if ((rc = grow(&x.pkeys, pcap)) || (rc = grow(&x.pcount, pcap))) return x.pcap = 0, rc;
+        x.pcap = pcap;
+    }
+    HIP_TRY(hipMemsetAsync(x.pkeys, 0xFF, sizeof(uint64_t) * pcap, stream), "clear table");
+    HIP_TRY(hipMemsetAsync(x.pcount, 0, sizeof(int32_t) * pcap, stream), "clear table");
+    HIP_TRY(launch_kmer_join(set_q, cap_q, x.kstart, x.rlist, mode, x.pkeys, x.pcount, pcap, x.counters, stream),
+            "discover launch");
+
+    // 5. pairs at or above the threshold
+    HIP_TRY(launch_kmer_compact(x.pkeys, x.pcount, pcap, min_shared, pairs_out_dev, shared_out_dev, out_cap,
+                                x.counters, stream),
+            "discover launch");
+    if ((rc = read_counters(x, stream))) return rc;
+    *n_found = (int64_t)x.host[kKmOut];
+    return *n_found > out_cap ? SW_ENOMEM : SW_OK;
 }
 
 int sw_check(void* stream)

@@ -103,3 +103,24 @@ def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(sw, "_lib", None)
     with pytest.raises(ImportError):
         sw.lib()
+
+
+def _discover_raw(n_q=10, n_r=10, k=6, t=2, mode=0, cap=0, out=False, null=False, found=True):
+    L = sw.lib()
+    p = ctypes.c_void_p(0 if null else 0x1000)
+    o = ctypes.c_void_p(0x2000 if out else 0)
+    n = ctypes.c_int64(-1)
+    rc = L.sw_discover(p, p, n_q, p, p, n_r, k, t, mode, o, None, cap,
+                       ctypes.byref(n) if found else None, None)
+    return rc, n.value
+
+
+def test_discover_argument_checks_precede_device_use():
+    assert _discover_raw(found=False)[0] == sw.SW_EINVAL
+    for kw in ({"k": 0}, {"k": 7}, {"t": 0}, {"mode": 3}, {"mode": -1}, {"cap": -1},
+               {"mode": 1, "n_r": 9}, {"mode": 2, "n_q": 3}, {"cap": 5}, {"n_q": -1}):
+        assert _discover_raw(**kw) == (sw.SW_EINVAL, 0), kw
+    assert _discover_raw(n_q=1 << 31) == (sw.SW_ERANGE, 0)
+    assert _discover_raw(n_q=0) == (sw.SW_OK, 0)                  # nothing to do
+    assert _discover_raw(n_r=0, cap=4, out=True) == (sw.SW_OK, 0)
+    assert _discover_raw(null=True) == (sw.SW_EINVAL, 0)
