@@ -156,10 +156,11 @@ __global__ void __launch_bounds__(256) k_insert(KmerSide s, int k, uint64_t* __r
 // Exclusive scan of the per-k-mer counts over the dense k-mer space, in three
 // launches: per-tile totals, a scan of the totals, and the per-tile scan that
 // writes the starts (and clears the counts, which the scatter reuses as fill
-// cursors).  A tile is 256 threads x 16 counts.
+// cursors).  A tile is 16 rounds of 256 consecutive counts; thread t takes
+// element t of each round, so every load and store is coalesced.
 constexpr int kScanThreads = 256;
-constexpr int kScanPerThread = 16;
-constexpr int kScanTile = kScanThreads * kScanPerThread;
+constexpr int kScanRounds = 16;
+constexpr int kScanTile = kScanThreads * kScanRounds;
 
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* total)
 {
@@ -184,15 +185,31 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* tota
     return before + incl - v;
 }
 
+// Sum over the block, returned on every thread.
+__device__ __forceinline__ int64_t block_sum(int64_t v)
+{
+    __shared__ int64_t wsum[kScanThreads / 64];
+    v = (int64_t)wave_sum((uint64_t)v);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t all = 0;
+#pragma unroll
+    for (int i = 0; i < kScanThreads / 64; ++i) all += wsum[i];
+    __syncthreads();
+    return all;
+}
+
 __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t* __restrict__ kcount, int64_t n,
                                                              int64_t* __restrict__ tile_sums)
 {
-    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
     int64_t s = 0;
-    for (int i = 0; i < kScanPerThread; ++i)
-        if (first + i < n) s += kcount[first + i];
-    int64_t total;
-    (void)block_exclusive_scan(s, &total);
+#pragma unroll 4
+    for (int r = 0; r < kScanRounds; ++r) {
+        const int64_t i = first + (int64_t)r * kScanThreads;
+        if (i < n) s += kcount[i];
+    }
+    const int64_t total = block_sum(s);
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
@@ -217,21 +234,25 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(int32_t* __restrict
                                                              const int64_t* __restrict__ tile_sums,
                                                              int32_t* __restrict__ kstart)
 {
-    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
-    int32_t v[kScanPerThread];
-    int64_t s = 0;
-    for (int i = 0; i < kScanPerThread; ++i) {
-        v[i] = first + i < n ? kcount[first + i] : 0;
-        s += v[i];
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+    int32_t v[kScanRounds];
+#pragma unroll
+    for (int r = 0; r < kScanRounds; ++r) {
+        const int64_t i = first + (int64_t)r * kScanThreads;
+        v[r] = i < n ? kcount[i] : 0;
     }
-    int64_t total;
-    int64_t run = tile_sums[blockIdx.x] + block_exclusive_scan(s, &total);
-    for (int i = 0; i < kScanPerThread; ++i)
-        if (first + i < n) {
-            kstart[first + i] = (int32_t)run;
-            kcount[first + i] = 0;
-            run += v[i];
+    int64_t run = tile_sums[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kScanRounds; ++r) {
+        const int64_t i = first + (int64_t)r * kScanThreads;
+        int64_t total;
+        const int64_t ex = block_exclusive_scan(v[r], &total);
+        if (i < n) {
+            kstart[i] = (int32_t)(run + ex);
+            kcount[i] = 0;
         }
+        run += total;
+    }
 }
 
 __global__ void k_scatter(const uint64_t* __restrict__ set, int64_t cap, const int32_t* __restrict__ kstart,
@@ -248,19 +269,20 @@ __global__ void k_scatter(const uint64_t* __restrict__ set, int64_t cap, const i
 }
 
 // ---------------------------------------------------------------- 4. join
-__global__ void k_products(const uint64_t* __restrict__ set, int64_t cap, const int32_t* __restrict__ kstart,
-                           uint64_t* counters)
+// Grid-stride over the query entries with a fixed grid: one atomic per block.
+__global__ void __launch_bounds__(kScanThreads) k_products(const uint64_t* __restrict__ set, int64_t cap,
+                                                           const int32_t* __restrict__ kstart, uint64_t* counters)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    uint64_t s = 0;
+    int64_t s = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride) {
         const uint64_t key = set[i];
         if (key == kEmptyKey) continue;
         const uint32_t x = (uint32_t)key;
-        s += (uint64_t)(kstart[x + 1] - kstart[x]);
+        s += kstart[x + 1] - kstart[x];
     }
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long*)&counters[kKmProducts], (unsigned long long)s);
+    s = block_sum(s);
+    if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)&counters[kKmProducts], (unsigned long long)s);
 }
 
 // Pair filter of a self search: 0 keeps all, 1 the strict upper triangle,
@@ -310,31 +332,41 @@ __global__ void k_join(const uint64_t* __restrict__ qset, int64_t qcap, const in
 }
 
 // ---------------------------------------------------------------- 5. compact
-__global__ void k_compact(const uint64_t* __restrict__ pkeys, const int32_t* __restrict__ pcount, int64_t pcap,
-                          int min_shared, int32_t* __restrict__ pairs_out, int32_t* __restrict__ shared_out,
-                          int64_t out_cap, uint64_t* counters)
+// Each wave owns a segment of kCompactSeg consecutive slots: it counts its
+// hits, reserves that many output places with one atomic, then writes them in
+// slot order.  (One atomic per wave and 64 slots made that single counter the
+// bottleneck.)
+constexpr int kCompactRounds = 32;
+constexpr int kCompactSeg = 64 * kCompactRounds;
+
+__global__ void __launch_bounds__(256) k_compact(const uint64_t* __restrict__ pkeys,
+                                                 const int32_t* __restrict__ pcount, int64_t pcap, int min_shared,
+                                                 int32_t* __restrict__ pairs_out, int32_t* __restrict__ shared_out,
+                                                 int64_t out_cap, uint64_t* counters)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // whole waves iterate together so that the ballot below sees every lane
-    const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t end = (pcap + 63) & ~(int64_t)63;
-    for (int64_t i = start; i < end; i += stride) {
-        bool hit = false;
+    const int64_t seg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t first = seg * kCompactSeg + lane;
+    uint32_t hits = 0;
+    for (int r = 0; r < kCompactRounds; ++r) {
+        const int64_t i = first + (int64_t)r * 64;
+        const bool hit = i < pcap && pkeys[i] != kEmptyKey && pcount[i] >= min_shared;
+        hits += (uint32_t)__popcll(__ballot(hit));
+    }
+    if (hits == 0) return;  // wave-uniform
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long*)&counters[kKmOut], (unsigned long long)hits);
+    base = __shfl(base, 0, 64);
+    for (int r = 0; r < kCompactRounds; ++r) {
+        const int64_t i = first + (int64_t)r * 64;
         uint64_t key = kEmptyKey;
         int32_t c = 0;
         if (i < pcap) {
             key = pkeys[i];
             c = pcount[i];
-            hit = key != kEmptyKey && c >= min_shared;
         }
+        const bool hit = key != kEmptyKey && c >= min_shared;
         const uint64_t m = __ballot(hit);
-        if (!m) continue;
-        uint64_t base = 0;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        if (lane == leader)
-            base = atomicAdd((unsigned long long*)&counters[kKmOut], (unsigned long long)__popcll(m));
-        base = __shfl(base, leader, 64);
         if (hit) {
             const uint64_t at = base + __popcll(m & ((1ull << lane) - 1ull));
             if (at < (uint64_t)out_cap) {
@@ -343,6 +375,7 @@ __global__ void k_compact(const uint64_t* __restrict__ pkeys, const int32_t* __r
                 if (shared_out) shared_out[at] = c;
             }
         }
+        base += __popcll(m);
     }
 }
 
@@ -399,7 +432,7 @@ hipError_t launch_kmer_scatter(const uint64_t* set, int64_t set_cap, const int32
 hipError_t launch_kmer_products(const uint64_t* set, int64_t set_cap, const int32_t* kstart, uint64_t* counters,
                                 hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_products, dim3(grid_for(set_cap, 256)), dim3(256), 0, stream, set, set_cap, kstart,
+    hipLaunchKernelGGL(k_products, dim3(grid_for(set_cap, 256, 2048)), dim3(256), 0, stream, set, set_cap, kstart,
                        counters);
     return hipGetLastError();
 }
@@ -417,8 +450,10 @@ hipError_t launch_kmer_compact(const uint64_t* pkeys, const int32_t* pcount, int
                                int32_t* pairs_out, int32_t* shared_out, int64_t out_cap, uint64_t* counters,
                                hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(pcap, 256)), dim3(256), 0, stream, pkeys, pcount, pcap, min_shared,
-                       pairs_out, shared_out, out_cap, counters);
+    // four waves per block, one segment per wave
+    const int64_t segs = (pcap + kCompactSeg - 1) / kCompactSeg;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((segs + 3) / 4)), dim3(256), 0, stream, pkeys, pcount, pcap,
+                       min_shared, pairs_out, shared_out, out_cap, counters);
     return hipGetLastError();
 }
 
