@@ -9,7 +9,8 @@ its own C source (``sw_oracle.c``), its own substitution table parsed from
 The recurrence, the gap model and the tie rule are stated in the header of
 ``sw_oracle.c``; candidate discovery (distinct shared k-mers, the overlap
 product of the k-mer matrix with itself) in the header of
-``discover_oracle.c`` (the paper, section "Load balancing techniques": the aligner
+``discover_oracle.c``; identity and coverage of aligned pairs (the
+similarity-graph filter) in the header of ``identity_oracle.c`` (the paper, section "Load balancing techniques": the aligner
 fills the entire dynamic-programming matrix; "Performance results", program
 parameter table: affine gap open / extension penalties, integer scores).
 """
@@ -27,6 +28,8 @@ SRC = os.path.join(HERE, "sw_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 DISCOVER_SRC = os.path.join(HERE, "discover_oracle.c")
 DISCOVER_LIB = os.path.join(HERE, "liboracle_discover.so")
+IDENTITY_SRC = os.path.join(HERE, "identity_oracle.c")
+IDENTITY_LIB = os.path.join(HERE, "liboracle_identity.so")
 MATRIX_TXT = os.path.join(HERE, "blosum62.txt")
 
 
@@ -46,7 +49,7 @@ def compile_oracle(src: str, out: str) -> str:
 
 
 def build(force: bool = True) -> str:
-    for src, lib in ((SRC, LIB), (DISCOVER_SRC, DISCOVER_LIB)):
+    for src, lib in ((SRC, LIB), (DISCOVER_SRC, DISCOVER_LIB), (IDENTITY_SRC, IDENTITY_LIB)):
         if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
             compile_oracle(src, lib)
     return LIB
@@ -257,3 +260,67 @@ def discover(q_ascii, q_offs, r_ascii, r_offs, k: int = 6, min_shared: int = 2, 
 def distinct_kmers(ascii, offs, k: int = 6) -> np.ndarray:
     """Number of distinct k-mers of every sequence."""
     return discover_lib().distinct_kmers_codes(_ascii_codes(ascii), offs, k)
+
+
+class IdentityLib:
+    """ctypes view of one compiled identity oracle (the default build, or a
+    deliberately altered copy used to show that its pins catch mistakes)."""
+
+    def __init__(self, path: str):
+        L = ctypes.CDLL(path)
+        L.oracle_identity_box.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_identity_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+        self.L = L
+
+    def box(self, q, r, scores, go: int = 11, ge: int = 1):
+        """(score, matches, columns) of the best global alignment of two code
+        arrays (higher score, then more matches, then fewer columns)."""
+        qc = np.ascontiguousarray(q, dtype=np.int8)
+        rc_ = np.ascontiguousarray(r, dtype=np.int8)
+        sc = np.ascontiguousarray(scores, dtype=np.int8).reshape(-1)
+        s, m, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        if self.L.oracle_identity_box(qc.ctypes.data, len(qc), rc_.ctypes.data, len(rc_), sc.ctypes.data, go, ge,
+                                      ctypes.byref(s), ctypes.byref(m), ctypes.byref(c)) != 0:
+            raise ValueError("oracle_identity_box failed")
+        return s.value, m.value, c.value
+
+    def batch(self, codes, offsets, pairs, aligned, scores, go: int = 11, ge: int = 1,
+              ani_permille: int = 300, cov_permille: int = 700) -> np.ndarray:
+        """int64 [n_pairs, 4]: box score, matches, columns, keep."""
+        codes = np.ascontiguousarray(codes, dtype=np.int8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        aligned = np.ascontiguousarray(aligned, dtype=np.int32).reshape(-1, 5)
+        sc = np.ascontiguousarray(scores, dtype=np.int8).reshape(-1)
+        out = np.zeros((len(pairs), 4), dtype=np.int64)
+        if self.L.oracle_identity_batch(codes.ctypes.data, offsets.ctypes.data, len(offsets) - 1,
+                                        pairs.ctypes.data, len(pairs), aligned.ctypes.data, sc.ctypes.data,
+                                        go, ge, ani_permille, cov_permille, out.ctypes.data) != 0:
+            raise ValueError("oracle_identity_batch failed")
+        return out
+
+
+_identity = None
+
+
+def identity_lib() -> IdentityLib:
+    global _identity
+    with _lock:
+        if _identity is None:
+            build(force=False)
+            _identity = IdentityLib(IDENTITY_LIB)
+    return _identity
+
+
+def identity_ascii(ascii, offsets, pairs, aligned, go: int = 11, ge: int = 1, ani_permille: int = 300,
+                   cov_permille: int = 700) -> np.ndarray:
+    """Identity filter records (see ``IdentityLib.batch``) of aligned pairs of
+    an ASCII sequence buffer, encoded with the oracle's own encoder."""
+    codes = _ascii_codes(ascii)
+    return identity_lib().batch(codes, offsets, pairs, aligned, default().scores, go, ge, ani_permille,
+                                cov_permille)
