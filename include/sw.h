@@ -266,6 +266,49 @@ SW_API int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, i
                        int32_t k, int32_t min_shared, int32_t mode, int32_t* pairs_out_dev,
                        int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found, void* stream);
 
+/* ------------------------------------------------------ identity and coverage
+ * The alignment metrics the paper forms its similarity graph from (section
+ * "Protein similarity search pipeline": identity and coverage of each
+ * aligned pair, kept above thresholds -- 0.30 and 0.70 in the program
+ * parameters of section "Similarity search at scale").
+ *
+ * For every pair whose aligned score (aligned_dev, this library's results for
+ * the same pairs, sets and scoring) is positive, the pass takes the box the
+ * aligner reported, q[q_start..q_end] x r[r_start..r_end], and among all
+ * global alignments of that box picks the best by score, then by the number
+ * of identical aligned pairs, then by the fewest columns (aligned pairs plus
+ * gap positions).  Its score equals the aligned score.  The record holds
+ * that score, the matches, the columns, and keep = 1 when
+ *   1000 * matches >= ani_permille * columns,
+ *   1000 * (q_end - q_start + 1) >= cov_permille * (query length), and
+ *   1000 * (r_end - r_start + 1) >= cov_permille * (reference length)
+ * (identity and both coverages at least the thresholds, given in
+ * thousandths; integer arithmetic).  A pair with score 0 gets all zeros.
+ *
+ * Sets, offsets and pairs as for sw_align_sets; out_dev receives n_pairs
+ * records.  Asynchronous on `stream` like sw_align_sets; with SW_VALIDATE the
+ * call synchronises and reports device-found errors.  Workspace: one scratch
+ * row pair of 65,536 int64 per resident wave (about 2 GiB on a 256-CU GPU),
+ * allocated on the first call on a stream and kept.
+ *
+ * Errors: SW_EINVAL (null pointer, bad scoring or flags, thresholds outside
+ * 0..1000), SW_ERANGE (pair index or coordinates outside the sequences, or a
+ * box whose best score differs from the aligned score: found on the device,
+ * reported under SW_VALIDATE or by sw_check), SW_ECODE, SW_ENOMEM, SW_EDEVICE.
+ */
+typedef struct {
+    int32_t score;   /* best global score of the box (the aligned score) */
+    int32_t matches; /* identical aligned pairs */
+    int32_t columns; /* aligned pairs plus gap positions */
+    int32_t keep;    /* 1: identity and both coverages reach the thresholds */
+} sw_identity_result;
+
+SW_API int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                       const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
+                       const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring,
+                       const sw_result* aligned_dev, int32_t ani_permille, int32_t cov_permille,
+                       sw_identity_result* out_dev, void* stream, uint32_t flags);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching against a reference set resident in HBM.  The server
  * keeps `max_slots` HIP streams, each with its own alignment workspace, and an

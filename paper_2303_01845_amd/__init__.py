@@ -36,7 +36,7 @@ EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_
            "sw_timing_read_passes", "sw_set_tuning",
            "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
            "sw_server_submit", "sw_server_poll", "sw_server_wait", "sw_server_stats",
-           "sw_server_request_bytes", "sw_server_destroy", "sw_discover")
+           "sw_server_request_bytes", "sw_server_destroy", "sw_discover", "sw_identity")
 
 DISCOVER_ALL = 0
 DISCOVER_UPPER = 1
@@ -110,6 +110,11 @@ def lib():
                                   ctypes.c_int64, ctypes.POINTER(Scoring), ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float)]
         L.sw_matrix.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_char_p]
+        L.sw_identity.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
+                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_uint32]
         L.sw_discover.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
@@ -285,6 +290,28 @@ def discover(q_packed, q_offsets, r_packed, r_offsets, k: int = 6, min_shared: i
                          int(capacity), ctypes.byref(found), st), "sw_discover")
     n = found.value
     return pairs[:n], shared[:n]
+
+
+def identity(q_packed, q_offsets, r_packed, r_offsets, pairs, aligned, gap_open: int = 11,
+             gap_extend: int = 1, ani_permille: int = 300, cov_permille: int = 700, flags: int = 0,
+             out=None, stream=None):
+    """Identity and coverage records of aligned pairs (sw_identity): int32
+    [n_pairs, 4] on the GPU -- box score, matches, columns, keep."""
+    import torch
+    n_pairs = int(pairs.shape[0]) if pairs.dim() == 2 else int(pairs.numel() // 2)
+    if out is None:
+        out = torch.empty((n_pairs, 4), dtype=torch.int32, device=pairs.device)
+    assert q_offsets.dtype == torch.int64 and r_offsets.dtype == torch.int64
+    assert pairs.dtype == torch.int32 and aligned.dtype == torch.int32 and out.dtype == torch.int32
+    assert pairs.is_contiguous() and aligned.is_contiguous() and out.is_contiguous()
+    sc = Scoring(0, int(gap_open), int(gap_extend))
+    _check(lib().sw_identity(ctypes.c_void_p(q_packed.data_ptr()), ctypes.c_void_p(q_offsets.data_ptr()),
+                             int(q_offsets.numel()) - 1, ctypes.c_void_p(r_packed.data_ptr()),
+                             ctypes.c_void_p(r_offsets.data_ptr()), int(r_offsets.numel()) - 1,
+                             ctypes.c_void_p(pairs.data_ptr()), n_pairs, ctypes.byref(sc),
+                             ctypes.c_void_p(aligned.data_ptr()), int(ani_permille), int(cov_permille),
+                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), int(flags)), "sw_identity")
+    return out
 
 
 class Batch:

@@ -6,9 +6,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsw_hip.so")
-SOURCES = [os.path.join(CSRC, "sw_device.hip"), os.path.join(CSRC, "sw_kmer.hip"),
+SOURCES = [os.path.join(CSRC, "sw_device.hip"), os.path.join(CSRC, "sw_kmer.hip"), os.path.join(CSRC, "sw_identity.hip"),
            os.path.join(CSRC, "sw_api.cpp"), os.path.join(CSRC, "sw_server.cpp")]
 HEADERS = [os.path.join(CSRC, "sw_internal.h"), os.path.join(CSRC, "kmer_internal.h"),
+           os.path.join(CSRC, "identity_internal.h"),
            os.path.join(os.path.dirname(HERE), "include", "sw.h")]
 
 FLAGS = [

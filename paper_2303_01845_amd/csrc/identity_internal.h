@@ -1,0 +1,38 @@
+// Internal declarations of the identity / coverage pass (sw_identity.hip),
+// used by the host layer (sw_api.cpp).  Not part of the public interface.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "sw_internal.h"
+
+namespace swk {
+
+constexpr int kIdentMaxCols = SW_MAX_SEQ_LEN + 1;  // scratch columns per wave (a box is at most this wide)
+constexpr int kIdentWavesPerBlock = 4;
+
+struct IdentArgs {
+    const uint32_t* qblk;
+    const PackedHeader* qhdr;
+    const int64_t* q_offsets;
+    int64_t n_q;
+    const uint32_t* rblk;
+    const PackedHeader* rhdr;
+    const int64_t* r_offsets;
+    int64_t n_r;
+    const int32_t* pairs;
+    int64_t n_pairs;
+    const sw_result* aligned;
+    sw_identity_result* out;
+    const int8_t* subst;    // [24 * 24] scores in the packed code order
+    int64_t* scratch;       // per wave: kIdentMaxCols H keys, then kIdentMaxCols F keys
+    int32_t* next_pair;     // work counter (zero before the launch)
+    int32_t* err;           // device error bits (kErr*)
+    int32_t go, ge;
+    int32_t ani_permille, cov_permille;
+};
+
+hipError_t launch_identity(const IdentArgs& a, int blocks, hipStream_t stream);
+
+}  // namespace swk

@@ -10,6 +10,7 @@
 #include <tuple>
 #include <vector>
 
+#include "identity_internal.h"
 #include "kmer_internal.h"
 #include "sw_internal.h"
 
@@ -205,6 +206,10 @@ struct Workspace {
     std::vector<int> timed_pass;  // per timed pair: 0 forward (plain: both passes), 1 start
     int64_t timed_calls = 0;
     std::unique_ptr<DiscoverSpace> discover;
+    int64_t* ident_scratch = nullptr;  // identity pass: two rows of columns per resident wave
+    int64_t ident_scratch_words = 0;
+    int32_t* ident_next = nullptr;     // its work counter
+    int8_t* ident_subst = nullptr;     // the matrix in packed-code order
 
     void drop_graphs()
     {
@@ -226,6 +231,9 @@ struct Workspace {
         (void)hipFree(rank_start);
         (void)hipFree(counters);
         (void)hipFree(scratch);
+        (void)hipFree(ident_scratch);
+        (void)hipFree(ident_next);
+        (void)hipFree(ident_subst);
         if (host_rank_start) (void)hipHostFree(host_rank_start);
     }
 };
@@ -733,6 +741,85 @@ int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     if ((rc = read_counters(x, stream))) return rc;
     *n_found = (int64_t)x.host[kKmOut];
     return *n_found > out_cap ? SW_ENOMEM : SW_OK;
+}
+
+int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+                const sw_scoring* scoring, const sw_result* aligned_dev, int32_t ani_permille, int32_t cov_permille,
+                sw_identity_result* out_dev, void* stream_, uint32_t flags)
+{
+    if (!scoring || n_pairs < 0 || n_q < 0 || n_r < 0) return SW_EINVAL;
+    if (flags & ~SW_VALIDATE) return SW_EINVAL;
+    if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
+        scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
+        return SW_EINVAL;
+    if (ani_permille < 0 || ani_permille > 1000 || cov_permille < 0 || cov_permille > 1000) return SW_EINVAL;
+    if (n_pairs == 0) return SW_OK;
+    if (!q_packed_dev || !q_offsets_dev || !r_packed_dev || !r_offsets_dev || !pairs_dev || !aligned_dev || !out_dev)
+        return SW_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(q_packed_dev) | reinterpret_cast<uintptr_t>(r_packed_dev)) & 15u)
+        return SW_EINVAL;
+    if (n_pairs > (int64_t)0x7FFFFFFF - (1 << 20) || n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF)
+        return SW_ERANGE;
+    hipStream_t stream = (hipStream_t)stream_;
+
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* dp = nullptr;
+    int rc = get_device(&dp);
+    if (rc) return rc;
+    Device& d = *dp;
+    Workspace* wp = nullptr;
+    if ((rc = get_workspace(d, stream, 0, &wp))) return rc;
+    Workspace& w = *wp;
+    if (!w.ident_subst) {
+        // the substitution matrix re-indexed by packed code
+        int8_t ncbi[kNumSym * kNumSym], coded[kNumSym * kNumSym];
+        char letters[kNumSym + 1];
+        matrix_ncbi(ncbi, letters);
+        const char* order = code_order();
+        int idx[kNumSym];
+        for (int a = 0; a < kNumSym; ++a) {
+            const char* p = std::strchr(letters, order[a]);
+            if (!p) return SW_EDEVICE;
+            idx[a] = (int)(p - letters);
+        }
+        for (int a = 0; a < kNumSym; ++a)
+            for (int b = 0; b < kNumSym; ++b) coded[a * kNumSym + b] = ncbi[idx[a] * kNumSym + idx[b]];
+        if ((rc = grow(&w.ident_subst, kNumSym * kNumSym)) || (rc = grow(&w.ident_next, 1))) return rc;
+        HIP_TRY(hipMemcpy(w.ident_subst, coded, sizeof(coded), hipMemcpyHostToDevice), "upload matrix");
+    }
+    const int blocks = d.n_cu * 2;  // two blocks of four waves per CU
+    const int64_t need = (int64_t)blocks * kIdentWavesPerBlock * 2 * kIdentMaxCols;
+    if (need > w.ident_scratch_words) {
+        if ((rc = grow(&w.ident_scratch, need))) return w.ident_scratch_words = 0, rc;
+        w.ident_scratch_words = need;
+    }
+    IdentArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.qblk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(q_packed_dev) + kHeaderBytes);
+    a.qhdr = reinterpret_cast<const PackedHeader*>(q_packed_dev);
+    a.q_offsets = q_offsets_dev;
+    a.n_q = n_q;
+    a.rblk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(r_packed_dev) + kHeaderBytes);
+    a.rhdr = reinterpret_cast<const PackedHeader*>(r_packed_dev);
+    a.r_offsets = r_offsets_dev;
+    a.n_r = n_r;
+    a.pairs = pairs_dev;
+    a.n_pairs = n_pairs;
+    a.aligned = aligned_dev;
+    a.out = out_dev;
+    a.subst = w.ident_subst;
+    a.scratch = w.ident_scratch;
+    a.next_pair = w.ident_next;
+    a.err = d.err;
+    a.go = scoring->gap_open;
+    a.ge = scoring->gap_extend;
+    a.ani_permille = ani_permille;
+    a.cov_permille = cov_permille;
+    HIP_TRY(hipMemsetAsync(w.ident_next, 0, sizeof(int32_t), stream), "clear counter");
+    HIP_TRY(launch_identity(a, blocks, stream), "identity launch");
+    if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
+    return SW_OK;
 }
 
 int sw_check(void* stream)

@@ -1,0 +1,228 @@
+// Identity and coverage of aligned pairs: the numbers the similarity-graph
+// filter keeps an edge by.
+//
+// The paper forms the similarity graph from alignment metrics -- identity and
+// coverage -- kept above thresholds (section "Protein similarity search
+// pipeline"; thresholds 0.30 and 0.70 in the program parameters of section
+// "Similarity search at scale").  Identity depends on which optimal alignment
+// is taken; this pass takes, over the box the aligner reported
+// (q[q_start..q_end] x r[r_start..r_end]), the global alignment that is best
+// first by score, then by the number of identical pairs, then by the fewest
+// columns, and reports its matches and columns.
+//
+// One wave per pair, pairs handed out by a counter.  The box is swept in
+// strips of 64 rows: lane l owns row 64 s + l and at step t computes column
+// t - l, so the cell above and the one above-left come from lane l-1's
+// previous two steps by lane shuffles.  The strip's bottom row (H and F) goes
+// to the wave's scratch row in global memory for the next strip; lane 0 reads
+// it 64 columns at a time, one chunk ahead, as it reads the reference codes.
+//
+// Each state holds one 64-bit key that orders alignments exactly as wanted:
+//   key = score << 40 | matches << 20 | (2^20 - 1 - columns)
+// Scores of kept cells are positive and below 2^20, matches and columns below
+// 2^20, so the fields never borrow from one another and integer order of keys
+// is the wanted lexicographic order; keys add along a path.  A cell whose
+// best score is not positive is dropped (key -2^62): every proper prefix of
+// an optimal alignment that starts at the reported start scores above zero
+// (otherwise a later start would be optimal too, and the reported start is
+// the latest one), so no dropped cell lies on an alignment that can win.
+#include "identity_internal.h"
+
+namespace swk {
+
+namespace {
+
+constexpr int64_t kNegKey = -(int64_t(1) << 62);
+constexpr int kScoreShift = 40;
+constexpr int kMatchShift = 20;
+constexpr int64_t kFieldMask = (int64_t(1) << 20) - 1;
+constexpr int64_t kOriginKey = kFieldMask;  // score 0, no matches, no columns
+
+__device__ __forceinline__ uint32_t code_at(const uint32_t* __restrict__ nib, const uint32_t* __restrict__ hib,
+                                            int64_t pos)
+{
+    const int64_t q = pos + kGuardRes;
+    const uint32_t lo = (nib[q >> 3] >> (4 * (uint32_t)(q & 7))) & 15u;
+    const uint32_t hi = (hib[q >> 5] >> (uint32_t)(q & 31)) & 1u;
+    return lo | (hi << 4);
+}
+
+__device__ __forceinline__ int64_t cut(int64_t k) { return (k >> kScoreShift) > 0 ? k : kNegKey; }
+__device__ __forceinline__ int64_t kmax(int64_t a, int64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ int64_t shfl_up64(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)u, 1, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(u >> 32), 1, 64);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)u, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(u >> 32), src, 64);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs a)
+{
+    __shared__ int8_t sub[kNumSym * kNumSym];
+    for (int i = threadIdx.x; i < kNumSym * kNumSym; i += blockDim.x) sub[i] = a.subst[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * kIdentWavesPerBlock + (threadIdx.x >> 6);
+    int64_t* Hrow = a.scratch + wave * (2 * (int64_t)kIdentMaxCols);
+    int64_t* Frow = Hrow + kIdentMaxCols;
+    const uint32_t* qnib = a.qblk;
+    const uint32_t* qhib = a.qblk + a.qhdr->n_blocks * 32;
+    const uint32_t* rnib = a.rblk;
+    const uint32_t* rhib = a.rblk + a.rhdr->n_blocks * 32;
+    const int64_t q_res = a.qhdr->n_residues, r_res = a.rhdr->n_residues;
+    const int64_t GO = ((int64_t)a.go << kScoreShift) + 1;  // gap costs, one column each
+    const int64_t GE = ((int64_t)a.ge << kScoreShift) + 1;
+    bool bad_range = false, bad_code = false, bad_box = false;
+
+    for (;;) {
+        int k = 0;
+        if (lane == 0) k = atomicAdd(a.next_pair, 1);
+        k = __shfl(k, 0, 64);
+        if ((int64_t)k >= a.n_pairs) break;
+        const sw_result res = a.aligned[k];
+        sw_identity_result rec = {0, 0, 0, 0};
+        bool ok = res.score > 0;
+        int64_t qb = 0, rb = 0, m = 0, n = 0;
+        if (ok) {
+            const int64_t qi = a.pairs[2 * (int64_t)k], ri = a.pairs[2 * (int64_t)k + 1];
+            if (qi < 0 || qi >= a.n_q || ri < 0 || ri >= a.n_r) {
+                ok = false;
+            } else {
+                qb = a.q_offsets[qi];
+                m = a.q_offsets[qi + 1] - qb;
+                rb = a.r_offsets[ri];
+                n = a.r_offsets[ri + 1] - rb;
+                ok = qb >= 0 && m >= 0 && qb + m <= q_res && rb >= 0 && n >= 0 && rb + n <= r_res &&
+                     m <= SW_MAX_SEQ_LEN && n <= SW_MAX_SEQ_LEN && res.q_start >= 0 && res.q_end >= res.q_start &&
+                     res.q_end < m && res.r_start >= 0 && res.r_end >= res.r_start && res.r_end < n;
+            }
+            bad_range = bad_range || !ok;
+        }
+        if (!ok) {
+            if (lane == 0) a.out[k] = rec;
+            continue;
+        }
+        const int M = res.q_end - res.q_start + 1, N = res.r_end - res.r_start + 1;
+        const int64_t Q0 = qb + res.q_start, R0 = rb + res.r_start;
+        const int n_strips = (M + 63) / 64;
+        int64_t fin = kNegKey;
+        for (int st = 0; st < n_strips; ++st) {
+            const int i = st * 64 + lane;
+            const int rows = min(64, M - st * 64);
+            const bool row_ok = lane < rows;
+            uint32_t qc = row_ok ? code_at(qnib, qhib, Q0 + i) : 0u;
+            if (qc >= (uint32_t)kNumSym) {
+                bad_code = true;
+                qc = 0;
+            }
+            const int8_t* subrow = sub + qc * kNumSym;
+            int64_t E = kNegKey, Hleft = kNegKey;
+            int64_t diag_next = (lane == 0 && st == 0) ? kOriginKey : kNegKey;
+            int64_t outH = kNegKey, outF = kNegKey;
+            uint32_t rc_prev = 0;
+            // reference codes and the row above, 64 columns per chunk, one
+            // chunk ahead (reads past the box stay inside the padded buffer
+            // and the wave's scratch row; their values are never used)
+            uint32_t cur = code_at(rnib, rhib, R0 + lane);
+            uint32_t nxt = code_at(rnib, rhib, R0 + 64 + lane);
+            const bool above = st > 0;
+            int64_t curH = kNegKey, curF = kNegKey, nxtH = kNegKey, nxtF = kNegKey;
+            if (above) {
+                curH = Hrow[lane];
+                curF = Frow[lane];
+                nxtH = Hrow[min(64 + lane, kIdentMaxCols - 1)];
+                nxtF = Frow[min(64 + lane, kIdentMaxCols - 1)];
+            }
+            const int steps = N + rows - 1;
+            for (int t = 0; t < steps; ++t) {
+                if (t > 0 && (t & 63) == 0) {
+                    cur = nxt;
+                    nxt = code_at(rnib, rhib, R0 + t + 64 + lane);
+                    if (above) {
+                        curH = nxtH;
+                        curF = nxtF;
+                        const int c = min(t + 64 + lane, kIdentMaxCols - 1);
+                        nxtH = Hrow[c];
+                        nxtF = Frow[c];
+                    }
+                }
+                const uint32_t rc_new = (uint32_t)__shfl((int)cur, t & 63, 64);
+                const uint32_t rc_up = (uint32_t)__shfl_up((int)rc_prev, 1, 64);
+                const uint32_t rc = lane == 0 ? rc_new : rc_up;
+                rc_prev = rc;
+                int64_t upH = shfl_up64(outH);
+                int64_t upF = shfl_up64(outF);
+                const int64_t topH = shfl64(curH, t & 63);
+                const int64_t topF = shfl64(curF, t & 63);
+                if (lane == 0) {
+                    upH = (above && t < N) ? topH : kNegKey;
+                    upF = (above && t < N) ? topF : kNegKey;
+                }
+                const int64_t diag = diag_next;
+                diag_next = upH;
+                const int j = t - lane;
+                if (row_ok && j >= 0 && j < N) {
+                    uint32_t rcc = rc;
+                    if (rcc >= (uint32_t)kNumSym) {
+                        bad_code = true;
+                        rcc = 0;
+                    }
+                    const int64_t s = (int64_t)subrow[rcc];
+                    const int64_t step = (s << kScoreShift) + (qc == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
+                    const int64_t d = cut(diag + step);
+                    E = cut(kmax(E - GE, Hleft - GO));
+                    const int64_t F = cut(kmax(upF - GE, upH - GO));
+                    const int64_t H = kmax(d, kmax(E, F));
+                    Hleft = H;
+                    outH = H;
+                    outF = F;
+                    if (lane == 63 && st + 1 < n_strips) {
+                        Hrow[j] = H;
+                        Frow[j] = F;
+                    }
+                    if (i == M - 1 && j == N - 1) fin = H;
+                } else {
+                    outH = kNegKey;
+                    outF = kNegKey;
+                }
+            }
+            // the strip's bottom row is in memory before the next strip reads it
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        }
+        if (lane == ((M - 1) & 63)) {
+            if (fin >= 0) {
+                rec.score = (int32_t)(fin >> kScoreShift);
+                rec.matches = (int32_t)((fin >> kMatchShift) & kFieldMask);
+                rec.columns = (int32_t)(kFieldMask - (fin & kFieldMask));
+                rec.keep = (1000 * (int64_t)rec.matches >= (int64_t)a.ani_permille * rec.columns) &&
+                           (1000 * (int64_t)M >= (int64_t)a.cov_permille * m) &&
+                           (1000 * (int64_t)N >= (int64_t)a.cov_permille * n);
+            }
+            if (rec.score != res.score) bad_box = true;
+            a.out[k] = rec;
+        }
+    }
+    int bits = (bad_range || bad_box ? kErrRange : 0) | (bad_code ? kErrCode : 0);
+    if (bits) atomicOr(a.err, bits);
+}
+
+}  // namespace
+
+hipError_t launch_identity(const IdentArgs& a, int blocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_identity, dim3((unsigned)blocks), dim3(64 * kIdentWavesPerBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace swk

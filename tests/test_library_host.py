@@ -124,3 +124,22 @@ def test_discover_argument_checks_precede_device_use():
     assert _discover_raw(n_q=0) == (sw.SW_OK, 0)                  # nothing to do
     assert _discover_raw(n_r=0, cap=4, out=True) == (sw.SW_OK, 0)
     assert _discover_raw(null=True) == (sw.SW_EINVAL, 0)
+
+
+def _identity_raw(go=11, ge=1, n_pairs=3, ani=300, cov=700, flags=0, null=False):
+    L = sw.lib()
+    sc = sw.Scoring(0, go, ge)
+    p = ctypes.c_void_p(0 if null else 0x1000)
+    return L.sw_identity(p, p, 10, p, p, 10, p, n_pairs, ctypes.byref(sc), p, ani, cov, p, None, flags)
+
+
+def test_identity_argument_checks_precede_device_use():
+    assert _identity_raw(n_pairs=0) == sw.SW_OK
+    assert _identity_raw(go=0, ge=0) == sw.SW_EINVAL
+    assert _identity_raw(go=2, ge=3) == sw.SW_EINVAL
+    assert _identity_raw(ani=-1) == sw.SW_EINVAL
+    assert _identity_raw(cov=1001) == sw.SW_EINVAL
+    assert _identity_raw(flags=sw.PLAIN) == sw.SW_EINVAL
+    assert _identity_raw(n_pairs=-1) == sw.SW_EINVAL
+    assert _identity_raw(null=True) == sw.SW_EINVAL
+    assert _identity_raw(n_pairs=1 << 31) == sw.SW_ERANGE
