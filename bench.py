@@ -236,12 +236,49 @@ def main():
                          "(whole application, multi-node; not a 1-GPU target)",
     }
     if args.workload == "block-50kx50k":
+        res["identity"] = identity_bench(sw, torch, ps, packed_d, offs_d, pairs_d, out_d, stream, args)
         res["discovery"] = discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args)
         res["discovery"]["pipeline_gcups"] = round(
             cells / ((res["discovery"]["ms"] + ms_per_step) * 1e-3) / 1e9, 2)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def identity_bench(sw, torch, ps, packed_d, offs_d, pairs_d, out_d, stream, args):
+    """The identity / coverage pass (sw_identity, thresholds 0.30 and 0.70)
+    over the aligned block workload: HIP-event time per call, the cells of the
+    boxes it sweeps, the kept count, and a sample against the oracle."""
+    import oracle
+    rec = torch.empty((ps.n_pairs, 4), dtype=torch.int32, device=out_d.device)
+    for _ in range(2):
+        sw.identity(packed_d, offs_d, packed_d, offs_d, pairs_d, out_d, 11, 1, 300, 700, flags=sw.VALIDATE,
+                    out=rec, stream=stream)
+    steps = max(3, args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        sw.identity(packed_d, offs_d, packed_d, offs_d, pairs_d, out_d, 11, 1, 300, 700, out=rec, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sw.check(stream)
+    ms = e0.elapsed_time(e1) / steps
+    a = out_d.cpu().numpy()
+    got = rec.cpu().numpy()
+    box = int(((a[:, 2] - a[:, 1] + 1).astype(np.int64) * (a[:, 4] - a[:, 3] + 1))[a[:, 0] > 0].sum())
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(ps.n_pairs, min(1000, ps.n_pairs), replace=False))
+    sub = ps.subset(sample)
+    exp_aln = oracle.batch_ascii(sub.ascii, sub.offsets, sub.pairs, 11, 1)
+    exp = oracle.identity_ascii(sub.ascii, sub.offsets, sub.pairs, exp_aln, 11, 1, 300, 700)
+    n_ok = int((got[sample] == exp).all(axis=1).sum())
+    log("identity: %.3f ms per call, %.3f Gcells of boxes, %d of %d kept, sample %d/%d" % (
+        ms, box / 1e9, int(got[:, 3].sum()), ps.n_pairs, n_ok, len(sample)))
+    return {"ms": round(ms, 3), "box_cells": box, "box_gcups": round(box / (ms * 1e-3) / 1e9, 2),
+            "kept": int(got[:, 3].sum()), "pairs": ps.n_pairs, "steps": steps,
+            "thresholds": "identity >= 0.300, both coverages >= 0.700",
+            "parity_sample": "%d/%d equal to the oracle" % (n_ok, len(sample))}
 
 
 def discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args):

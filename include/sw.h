@@ -288,7 +288,7 @@ SW_API int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, i
  * Sets, offsets and pairs as for sw_align_sets; out_dev receives n_pairs
  * records.  Asynchronous on `stream` like sw_align_sets; with SW_VALIDATE the
  * call synchronises and reports device-found errors.  Workspace: one scratch
- * row pair of 65,536 int64 per resident wave (about 2 GiB on a 256-CU GPU),
+ * row pair of 65,536 int64 per resident wave (4 GiB on a 256-CU GPU),
  * allocated on the first call on a stream and kept.
  *
  * Errors: SW_EINVAL (null pointer, bad scoring or flags, thresholds outside

@@ -788,7 +788,7 @@ int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
         if ((rc = grow(&w.ident_subst, kNumSym * kNumSym)) || (rc = grow(&w.ident_next, 1))) return rc;
         HIP_TRY(hipMemcpy(w.ident_subst, coded, sizeof(coded), hipMemcpyHostToDevice), "upload matrix");
     }
-    const int blocks = d.n_cu * 2;  // two blocks of four waves per CU
+    const int blocks = d.n_cu * 4;  // four blocks of four waves per CU: four waves per SIMD
     const int64_t need = (int64_t)blocks * kIdentWavesPerBlock * 2 * kIdentMaxCols;
     if (need > w.ident_scratch_words) {
         if ((rc = grow(&w.ident_scratch, need))) return w.ident_scratch_words = 0, rc;

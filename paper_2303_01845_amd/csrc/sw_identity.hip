@@ -58,11 +58,17 @@ __device__ __forceinline__ int64_t shfl_up64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ int64_t shfl64(int64_t v, int src)
+// Value of lane `src` (wave-uniform) on every lane, without going through LDS.
+__device__ __forceinline__ uint32_t readlane32(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int src)
 {
     const uint64_t u = (uint64_t)v;
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)u, src, 64);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(u >> 32), src, 64);
+    const uint32_t lo = readlane32((uint32_t)u, src);
+    const uint32_t hi = readlane32((uint32_t)(u >> 32), src);
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
@@ -81,8 +87,10 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
     const uint32_t* rnib = a.rblk;
     const uint32_t* rhib = a.rblk + a.rhdr->n_blocks * 32;
     const int64_t q_res = a.qhdr->n_residues, r_res = a.rhdr->n_residues;
-    const int64_t GO = ((int64_t)a.go << kScoreShift) + 1;  // gap costs, one column each
-    const int64_t GE = ((int64_t)a.ge << kScoreShift) + 1;
+    // gap steps as keys to add: minus the cost in the score field, one column
+    // more (a 64-bit add is one instruction, a subtraction two)
+    const int64_t GO = -(((int64_t)a.go << kScoreShift) + 1);
+    const int64_t GE = -(((int64_t)a.ge << kScoreShift) + 1);
     bool bad_range = false, bad_code = false, bad_box = false;
 
     for (;;) {
@@ -157,14 +165,18 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
                         nxtF = Frow[c];
                     }
                 }
-                const uint32_t rc_new = (uint32_t)__shfl((int)cur, t & 63, 64);
+                // lane 0's inputs (the new column's code, the row above) are
+                // read from one lane of the chunk; every other lane takes its
+                // left neighbour's values of the previous step
+                const int src = t & 63;
+                const uint32_t rc_new = readlane32(cur, src);
                 const uint32_t rc_up = (uint32_t)__shfl_up((int)rc_prev, 1, 64);
                 const uint32_t rc = lane == 0 ? rc_new : rc_up;
                 rc_prev = rc;
                 int64_t upH = shfl_up64(outH);
                 int64_t upF = shfl_up64(outF);
-                const int64_t topH = shfl64(curH, t & 63);
-                const int64_t topF = shfl64(curF, t & 63);
+                const int64_t topH = readlane64(curH, src);
+                const int64_t topF = readlane64(curF, src);
                 if (lane == 0) {
                     upH = (above && t < N) ? topH : kNegKey;
                     upF = (above && t < N) ? topF : kNegKey;
@@ -181,8 +193,8 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
                     const int64_t s = (int64_t)subrow[rcc];
                     const int64_t step = (s << kScoreShift) + (qc == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
                     const int64_t d = cut(diag + step);
-                    E = cut(kmax(E - GE, Hleft - GO));
-                    const int64_t F = cut(kmax(upF - GE, upH - GO));
+                    E = cut(kmax(E + GE, Hleft + GO));
+                    const int64_t F = cut(kmax(upF + GE, upH + GO));
                     const int64_t H = kmax(d, kmax(E, F));
                     Hleft = H;
                     outH = H;
