@@ -298,7 +298,7 @@ def discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args):
     call_args = (ctypes.c_void_p(packed_d.data_ptr()), ctypes.c_void_p(qo.data_ptr()), nq,
                  ctypes.c_void_p(packed_d.data_ptr()), ctypes.c_void_p(ro.data_ptr()), ps.n_seqs - nq, 6, 2,
                  sw.DISCOVER_ALL, ctypes.c_void_p(pairs.data_ptr()), ctypes.c_void_p(shared.data_ptr()), cap,
-                 ctypes.byref(found), ctypes.c_void_p(stream.cuda_stream))
+                 ctypes.byref(found), 0, ctypes.c_void_p(stream.cuda_stream))
     for _ in range(2):
         rc = L.sw_discover(*call_args)
         if rc:

@@ -251,6 +251,16 @@ SW_API int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters);
  * the number of k-mer matches, two int32 arrays of 24^k entries) grows to the
  * largest call seen on the stream and is kept for reuse.
  *
+ * table_budget_bytes bounds the (query, reference) counter table, the part
+ * that grows with the number of k-mer matches (12 bytes per slot, twice as
+ * many slots as matches, rounded up to a power of two).  0 means no bound.
+ * When the whole table would exceed it, the queries are cut into contiguous
+ * ranges whose tables fit, and each range is counted and written in a pass
+ * of its own (the overlap product formed block by block, as the paper does
+ * to bound the memory of discovery, section "Blocked 2D Sparse SUMMA").  A
+ * single query whose matches alone exceed the budget forms a range with a
+ * table of its own size.  The result does not depend on the budget.
+ *
  * Errors: SW_EINVAL (null pointer, k outside 1..6, min_shared < 1, unknown
  * mode, a self-search mode with n_q != n_r), SW_ERANGE (offsets not
  * increasing or beyond the packed buffer, 2^31 or more k-mer windows in the
@@ -264,7 +274,8 @@ SW_API int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters);
 SW_API int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
                        const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
                        int32_t k, int32_t min_shared, int32_t mode, int32_t* pairs_out_dev,
-                       int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found, void* stream);
+                       int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found,
+                       size_t table_budget_bytes, void* stream);
 
 /* ------------------------------------------------------ identity and coverage
  * The alignment metrics the paper forms its similarity graph from (section

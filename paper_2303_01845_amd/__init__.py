@@ -119,7 +119,7 @@ def lib():
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
-                                  ctypes.c_void_p]
+                                  ctypes.c_size_t, ctypes.c_void_p]
         L.sw_strerror.argtypes = [ctypes.c_int]
         L.sw_strerror.restype = ctypes.c_char_p
         L.sw_last_device_error.restype = ctypes.c_char_p
@@ -265,11 +265,12 @@ def matrix():
 
 
 def discover(q_packed, q_offsets, r_packed, r_offsets, k: int = 6, min_shared: int = 2,
-             mode: int = DISCOVER_ALL, capacity: int | None = None, stream=None):
+             mode: int = DISCOVER_ALL, capacity: int | None = None, table_budget: int = 0, stream=None):
     """Candidate pairs with at least ``min_shared`` distinct common k-mers
     (sw_discover).  Returns (pairs int32 [n, 2], shared int32 [n]) on the GPU,
     in unspecified order.  Without ``capacity`` the library is asked for the
-    count first; with it, a too-small capacity raises SW_ENOMEM."""
+    count first; with it, a too-small capacity raises SW_ENOMEM.
+    ``table_budget`` bounds the pair-counter table in bytes (0: no bound)."""
     import torch
     assert q_offsets.dtype == torch.int64 and r_offsets.dtype == torch.int64
     L = lib()
@@ -280,14 +281,14 @@ def discover(q_packed, q_offsets, r_packed, r_offsets, k: int = 6, min_shared: i
             ctypes.c_void_p(r_offsets.data_ptr()), int(r_offsets.numel()) - 1, int(k), int(min_shared), int(mode))
     found = ctypes.c_int64()
     if capacity is None:
-        status = L.sw_discover(*args, None, None, 0, ctypes.byref(found), st)
+        status = L.sw_discover(*args, None, None, 0, ctypes.byref(found), int(table_budget), st)
         if status not in (SW_OK, SW_ENOMEM):
             _check(status, "sw_discover")
         capacity = found.value
     pairs = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=dev)
     shared = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
     _check(L.sw_discover(*args, ctypes.c_void_p(pairs.data_ptr()), ctypes.c_void_p(shared.data_ptr()),
-                         int(capacity), ctypes.byref(found), st), "sw_discover")
+                         int(capacity), ctypes.byref(found), int(table_budget), st), "sw_discover")
     n = found.value
     return pairs[:n], shared[:n]
 

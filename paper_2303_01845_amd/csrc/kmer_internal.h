@@ -43,9 +43,12 @@ hipError_t launch_kmer_scatter(const uint64_t* set, int64_t set_cap, const int32
                                int32_t* rlist, hipStream_t stream);
 hipError_t launch_kmer_products(const uint64_t* set, int64_t set_cap, const int32_t* kstart, uint64_t* counters,
                                 hipStream_t stream);
+hipError_t launch_kmer_query_products(const uint64_t* set, int64_t set_cap, const int32_t* kstart, uint64_t* qprod,
+                                      hipStream_t stream);
+// joins only the query entries with q_lo <= q < q_hi
 hipError_t launch_kmer_join(const uint64_t* qset, int64_t qset_cap, const int32_t* kstart, const int32_t* rlist,
-                            int mode, uint64_t* pkeys, int32_t* pcount, int64_t pcap, uint64_t* counters,
-                            hipStream_t stream);
+                            int mode, int64_t q_lo, int64_t q_hi, uint64_t* pkeys, int32_t* pcount, int64_t pcap,
+                            uint64_t* counters, hipStream_t stream);
 hipError_t launch_kmer_compact(const uint64_t* pkeys, const int32_t* pcount, int64_t pcap, int min_shared,
                                int32_t* pairs_out, int32_t* shared_out, int64_t out_cap, uint64_t* counters,
                                hipStream_t stream);

@@ -157,6 +157,8 @@ struct DiscoverSpace {
     int64_t pcap = 0;
     uint64_t* counters = nullptr;
     uint64_t* host = nullptr;   // pinned copy of counters
+    uint64_t* qprod = nullptr;  // [n_q] k-mer matches per query (blocked form only)
+    int64_t qprod_cap = 0;
 
     ~DiscoverSpace()
     {
@@ -169,6 +171,7 @@ struct DiscoverSpace {
         (void)hipFree(pkeys);
         (void)hipFree(pcount);
         (void)hipFree(counters);
+        (void)hipFree(qprod);
         if (host) (void)hipHostFree(host);
     }
 };
@@ -635,7 +638,8 @@ int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n
 
 int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
                 const int64_t* r_offsets_dev, int64_t n_r, int32_t k, int32_t min_shared, int32_t mode,
-                int32_t* pairs_out_dev, int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found, void* stream_)
+                int32_t* pairs_out_dev, int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found,
+                size_t table_budget_bytes, void* stream_)
 {
     if (!n_found) return SW_EINVAL;
     *n_found = 0;
@@ -724,20 +728,60 @@ int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     HIP_TRY(launch_kmer_products(set_q, cap_q, x.kstart, x.counters, stream), "discover launch");
     if ((rc = read_counters(x, stream))) return rc;
     const int64_t products = (int64_t)x.host[kKmProducts];
-    const int64_t pcap = pow2_at_least(2 * products);
+    constexpr int64_t kSlotBytes = sizeof(uint64_t) + sizeof(int32_t);
+    // query ranges, each joined with its own pair table: one range unless the
+    // whole table would exceed the budget
+    std::vector<std::pair<int64_t, int64_t>> ranges;  // [q_lo, q_hi), table slots
+    std::vector<int64_t> range_cap;
+    if (table_budget_bytes == 0 || pow2_at_least(2 * products) * kSlotBytes <= (int64_t)table_budget_bytes) {
+        ranges.emplace_back(0, n_q);
+        range_cap.push_back(pow2_at_least(2 * products));
+    } else {
+        if (n_q > x.qprod_cap) {
+            if ((rc = grow(&x.qprod, n_q))) return x.qprod_cap = 0, rc;
+            x.qprod_cap = n_q;
+        }
+        HIP_TRY(hipMemsetAsync(x.qprod, 0, sizeof(uint64_t) * n_q, stream), "clear counts");
+        HIP_TRY(launch_kmer_query_products(set_q, cap_q, x.kstart, x.qprod, stream), "discover launch");
+        std::vector<uint64_t> qp((size_t)n_q);
+        HIP_TRY(hipMemcpyAsync(qp.data(), x.qprod, sizeof(uint64_t) * n_q, hipMemcpyDeviceToHost, stream),
+                "read counts");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        // the largest match count whose table (twice as many slots, a power
+        // of two) fits the budget; a query above it gets a range of its own
+        int64_t slots = 256;
+        while (slots * 2 * kSlotBytes <= (int64_t)table_budget_bytes) slots *= 2;
+        const int64_t per_range = std::max<int64_t>(slots / 2, 1);
+        int64_t lo = 0, acc = 0;
+        for (int64_t q = 0; q < n_q; ++q) {
+            if (q > lo && acc + (int64_t)qp[q] > per_range) {
+                ranges.emplace_back(lo, q);
+                range_cap.push_back(pow2_at_least(2 * acc));
+                lo = q;
+                acc = 0;
+            }
+            acc += (int64_t)qp[q];
+        }
+        ranges.emplace_back(lo, n_q);
+        range_cap.push_back(pow2_at_least(2 * acc));
+    }
+    const int64_t pcap = *std::max_element(range_cap.begin(), range_cap.end());
     if (pcap > x.pcap) {
         if ((rc = grow(&x.pkeys, pcap)) || (rc = grow(&x.pcount, pcap))) return x.pcap = 0, rc;
         x.pcap = pcap;
     }
-    HIP_TRY(hipMemsetAsync(x.pkeys, 0xFF, sizeof(uint64_t) * pcap, stream), "clear table");
-    HIP_TRY(hipMemsetAsync(x.pcount, 0, sizeof(int32_t) * pcap, stream), "clear table");
-    HIP_TRY(launch_kmer_join(set_q, cap_q, x.kstart, x.rlist, mode, x.pkeys, x.pcount, pcap, x.counters, stream),
-            "discover launch");
-
-    // 5. pairs at or above the threshold
-    HIP_TRY(launch_kmer_compact(x.pkeys, x.pcount, pcap, min_shared, pairs_out_dev, shared_out_dev, out_cap,
-                                x.counters, stream),
-            "discover launch");
+    for (size_t b = 0; b < ranges.size(); ++b) {
+        const int64_t cap_b = range_cap[b];
+        HIP_TRY(hipMemsetAsync(x.pkeys, 0xFF, sizeof(uint64_t) * cap_b, stream), "clear table");
+        HIP_TRY(hipMemsetAsync(x.pcount, 0, sizeof(int32_t) * cap_b, stream), "clear table");
+        HIP_TRY(launch_kmer_join(set_q, cap_q, x.kstart, x.rlist, mode, ranges[b].first, ranges[b].second, x.pkeys,
+                                 x.pcount, cap_b, x.counters, stream),
+                "discover launch");
+        // 5. pairs at or above the threshold (appended after earlier ranges')
+        HIP_TRY(launch_kmer_compact(x.pkeys, x.pcount, cap_b, min_shared, pairs_out_dev, shared_out_dev, out_cap,
+                                    x.counters, stream),
+                "discover launch");
+    }
     if ((rc = read_counters(x, stream))) return rc;
     *n_found = (int64_t)x.host[kKmOut];
     return *n_found > out_cap ? SW_ENOMEM : SW_OK;

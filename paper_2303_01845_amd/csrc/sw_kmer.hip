@@ -18,7 +18,9 @@
 //      dense space of 24^k k-mers (a histogram built during the insert, an
 //      exclusive scan, a scatter), giving the columns of A_r as lists;
 //   4. join: every query entry (q, x) walks the reference list of x and adds
-//      one to the (q, r) counter of a second hash table -- the semiring sum;
+//      one to the (q, r) counter of a second hash table -- the semiring sum
+//      (under a memory budget, one pass per range of queries, each with its
+//      own table: the product formed block by block);
 //   5. compact: counters at or above the threshold are written out.
 // Every hash probe loop stops after `capacity` probes; tables are sized at
 // least twice their largest possible occupancy, so a probe sequence always
@@ -285,6 +287,21 @@ __global__ void __launch_bounds__(kScanThreads) k_products(const uint64_t* __res
     if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)&counters[kKmProducts], (unsigned long long)s);
 }
 
+// Per-query number of k-mer matches (for splitting the join into query
+// ranges whose pair tables fit a memory budget).
+__global__ void k_query_products(const uint64_t* __restrict__ set, int64_t cap, const int32_t* __restrict__ kstart,
+                                 uint64_t* __restrict__ qprod)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride) {
+        const uint64_t key = set[i];
+        if (key == kEmptyKey) continue;
+        const uint32_t x = (uint32_t)key;
+        const int32_t len = kstart[x + 1] - kstart[x];
+        if (len > 0) atomicAdd((unsigned long long*)&qprod[key >> 32], (unsigned long long)len);
+    }
+}
+
 // Pair filter of a self search: 0 keeps all, 1 the strict upper triangle,
 // 2 the index-parity rule (below the diagonal equal parities, above it
 // different ones).
@@ -297,8 +314,9 @@ __device__ __forceinline__ bool keep_pair(uint32_t q, uint32_t r, int mode)
 }
 
 __global__ void k_join(const uint64_t* __restrict__ qset, int64_t qcap, const int32_t* __restrict__ kstart,
-                       const int32_t* __restrict__ rlist, int mode, uint64_t* __restrict__ pkeys,
-                       int32_t* __restrict__ pcount, uint64_t pmask, uint64_t* counters)
+                       const int32_t* __restrict__ rlist, int mode, uint32_t q_lo, uint32_t q_hi,
+                       uint64_t* __restrict__ pkeys, int32_t* __restrict__ pcount, uint64_t pmask,
+                       uint64_t* counters)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     bool full = false;
@@ -306,6 +324,7 @@ __global__ void k_join(const uint64_t* __restrict__ qset, int64_t qcap, const in
         const uint64_t key = qset[i];
         if (key == kEmptyKey) continue;
         const uint32_t q = (uint32_t)(key >> 32), x = (uint32_t)key;
+        if (q < q_lo || q >= q_hi) continue;  // another query range's pass
         const int32_t lo = kstart[x], hi = kstart[x + 1];
         for (int32_t e = lo; e < hi; ++e) {
             const uint32_t r = (uint32_t)rlist[e];
@@ -437,12 +456,20 @@ hipError_t launch_kmer_products(const uint64_t* set, int64_t set_cap, const int3
     return hipGetLastError();
 }
 
+hipError_t launch_kmer_query_products(const uint64_t* set, int64_t set_cap, const int32_t* kstart, uint64_t* qprod,
+                                      hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_query_products, dim3(grid_for(set_cap, 256)), dim3(256), 0, stream, set, set_cap, kstart,
+                       qprod);
+    return hipGetLastError();
+}
+
 hipError_t launch_kmer_join(const uint64_t* qset, int64_t qset_cap, const int32_t* kstart, const int32_t* rlist,
-                            int mode, uint64_t* pkeys, int32_t* pcount, int64_t pcap, uint64_t* counters,
-                            hipStream_t stream)
+                            int mode, int64_t q_lo, int64_t q_hi, uint64_t* pkeys, int32_t* pcount, int64_t pcap,
+                            uint64_t* counters, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_join, dim3(grid_for(qset_cap, 256)), dim3(256), 0, stream, qset, qset_cap, kstart, rlist,
-                       mode, pkeys, pcount, (uint64_t)(pcap - 1), counters);
+                       mode, (uint32_t)q_lo, (uint32_t)q_hi, pkeys, pcount, (uint64_t)(pcap - 1), counters);
     return hipGetLastError();
 }
 

@@ -36,8 +36,8 @@ def on_gpu(sw, asc, offs):
     return sw.pack(asc if len(asc) else b""), torch.from_numpy(offs).cuda()
 
 
-def gpu_triples(sw, qp, qo, rp, ro, k, t, mode=0, capacity=None):
-    pairs, shared = sw.discover(qp, qo, rp, ro, k, t, mode, capacity)
+def gpu_triples(sw, qp, qo, rp, ro, k, t, mode=0, capacity=None, budget=0):
+    pairs, shared = sw.discover(qp, qo, rp, ro, k, t, mode, capacity, budget)
     a = np.concatenate([pairs.cpu().numpy().reshape(-1, 2), shared.cpu().numpy().reshape(-1, 1)], 1)
     return a[np.lexsort((a[:, 1], a[:, 0]))] if len(a) else a.reshape(0, 3)
 
@@ -109,18 +109,18 @@ def test_capacity_and_errors(sw):
     args = (ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(rod.data_ptr()), len(rs),
             ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(rod.data_ptr()), len(rs), 3, 2, 1)
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    assert L.sw_discover(*args, None, None, 0, ctypes.byref(found), st) == sw.SW_ENOMEM
+    assert L.sw_discover(*args, None, None, 0, ctypes.byref(found), 0, st) == sw.SW_ENOMEM
     assert found.value == n
     buf = torch.full((n, 2), -7, dtype=torch.int32, device="cuda")
     assert L.sw_discover(*args, ctypes.c_void_p(buf.data_ptr()), None, n - 10, ctypes.byref(found),
-                         st) == sw.SW_ENOMEM
+                         0, st) == sw.SW_ENOMEM
     assert found.value == n
     got = buf[:n - 10].cpu().numpy()
     assert (buf[n - 10:].cpu().numpy() == -7).all()            # nothing beyond the capacity
     assert set(map(tuple, got)) <= set(map(tuple, exp[:, :2]))  # a subset of the answer
     assert len(set(map(tuple, got))) == n - 10
     # exact capacity, no shared counts requested
-    assert L.sw_discover(*args, ctypes.c_void_p(buf.data_ptr()), None, n, ctypes.byref(found), st) == sw.SW_OK
+    assert L.sw_discover(*args, ctypes.c_void_p(buf.data_ptr()), None, n, ctypes.byref(found), 0, st) == sw.SW_OK
     assert set(map(tuple, buf.cpu().numpy())) == set(map(tuple, exp[:, :2]))
     # offsets that run backwards, or past the packed residues
     bad = rod.clone()
@@ -180,3 +180,26 @@ def test_block_all_vs_all_full_size(sw):
     gen = ps.pairs.astype(np.int64)
     gen = gen[np.lexsort((gen[:, 1], gen[:, 0]))]
     assert np.array_equal(got[:, :2], np.stack([gen[:, 0], gen[:, 1] - nq], 1))
+
+
+def test_budget_splits_the_join(sw):
+    """A small pair-table budget forms the product query range by query range;
+    the result is the same set (here and on the full block set)."""
+    import torch
+    rng = np.random.default_rng(12)
+    rs = rand_set(rng, 300, "ACDE", 20, 120)
+    ra, ro = pack_set(rs)
+    rp, rod = on_gpu(sw, ra, ro)
+    for mode in (0, 1, 2):
+        exp = oracle_triples(ra, ro, ra, ro, 3, 2, mode)
+        for budget in (1, 4096, 1 << 16):
+            assert np.array_equal(gpu_triples(sw, rp, rod, rp, rod, 3, 2, mode, budget=budget), exp), (mode, budget)
+    ps = P.config_block()
+    nq = (ps.n_seqs + 1) // 2
+    packed = sw.pack(ps.ascii)
+    qo = torch.from_numpy(ps.offsets[:nq + 1].copy()).cuda()
+    ro = torch.from_numpy(ps.offsets[nq:].copy()).cuda()
+    full = gpu_triples(sw, packed, qo, packed, ro, 6, 2)
+    for budget in (64 << 20, 8 << 20):
+        say("block with a %d MiB table budget" % (budget >> 20))
+        assert np.array_equal(gpu_triples(sw, packed, qo, packed, ro, 6, 2, budget=budget), full)

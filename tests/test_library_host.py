@@ -111,7 +111,7 @@ def _discover_raw(n_q=10, n_r=10, k=6, t=2, mode=0, cap=0, out=False, null=False
     o = ctypes.c_void_p(0x2000 if out else 0)
     n = ctypes.c_int64(-1)
     rc = L.sw_discover(p, p, n_q, p, p, n_r, k, t, mode, o, None, cap,
-                       ctypes.byref(n) if found else None, None)
+                       ctypes.byref(n) if found else None, 0, None)
     return rc, n.value
 
 
