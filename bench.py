@@ -271,14 +271,20 @@ def identity_bench(sw, torch, ps, packed_d, offs_d, pairs_d, out_d, stream, args
     sample = np.sort(rng.choice(ps.n_pairs, min(1000, ps.n_pairs), replace=False))
     sub = ps.subset(sample)
     exp_aln = oracle.batch_ascii(sub.ascii, sub.offsets, sub.pairs, 11, 1)
+    t = time.perf_counter()
     exp = oracle.identity_ascii(sub.ascii, sub.offsets, sub.pairs, exp_aln, 11, 1, 300, 700)
+    cpu_s = time.perf_counter() - t
+    sa = exp_aln
+    sample_cells = int(((sa[:, 2] - sa[:, 1] + 1).astype(np.int64) * (sa[:, 4] - sa[:, 3] + 1))[sa[:, 0] > 0].sum())
     n_ok = int((got[sample] == exp).all(axis=1).sum())
     log("identity: %.3f ms per call, %.3f Gcells of boxes, %d of %d kept, sample %d/%d" % (
         ms, box / 1e9, int(got[:, 3].sum()), ps.n_pairs, n_ok, len(sample)))
     return {"ms": round(ms, 3), "box_cells": box, "box_gcups": round(box / (ms * 1e-3) / 1e9, 2),
             "kept": int(got[:, 3].sum()), "pairs": ps.n_pairs, "steps": steps,
             "thresholds": "identity >= 0.300, both coverages >= 0.700",
-            "parity_sample": "%d/%d equal to the oracle" % (n_ok, len(sample))}
+            "parity_sample": "%d/%d equal to the oracle" % (n_ok, len(sample)),
+            "oracle_cpu": {"box_gcups": round(sample_cells / cpu_s / 1e9, 4), "cores": 1, "kind": "oracle",
+                           "sample": "%d random pairs, %d box cells, %.2f s" % (len(sample), sample_cells, cpu_s)}}
 
 
 def discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args):
