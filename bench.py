@@ -277,12 +277,30 @@ def identity_bench(sw, torch, ps, packed_d, offs_d, pairs_d, out_d, stream, args
     sa = exp_aln
     sample_cells = int(((sa[:, 2] - sa[:, 1] + 1).astype(np.int64) * (sa[:, 4] - sa[:, 3] + 1))[sa[:, 0] > 0].sum())
     n_ok = int((got[sample] == exp).all(axis=1).sum())
-    log("identity: %.3f ms per call, %.3f Gcells of boxes, %d of %d kept, sample %d/%d" % (
-        ms, box / 1e9, int(got[:, 3].sum()), ps.n_pairs, n_ok, len(sample)))
+    # the same filter, sweeping only the pairs whose coverage passes
+    rec2 = torch.empty_like(rec)
+    sw.identity(packed_d, offs_d, packed_d, offs_d, pairs_d, out_d, 11, 1, 300, 700,
+                flags=sw.VALIDATE | sw.COVERAGE_FIRST, out=rec2, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        sw.identity(packed_d, offs_d, packed_d, offs_d, pairs_d, out_d, 11, 1, 300, 700, flags=sw.COVERAGE_FIRST,
+                    out=rec2, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sw.check(stream)
+    ms_cf = e0.elapsed_time(e1) / steps
+    got2 = rec2.cpu().numpy()
+    same_keep = bool(np.array_equal(got2[:, 3], got[:, 3]))
+    log("identity: %.3f ms per call, %.3f Gcells of boxes, %d of %d kept, sample %d/%d; coverage first %.3f ms "
+        "(%d swept, keep flags %s)" % (ms, box / 1e9, int(got[:, 3].sum()), ps.n_pairs, n_ok, len(sample), ms_cf,
+                                       int((got2[:, 1] >= 0).sum()), "equal" if same_keep else "DIFFERENT"))
     return {"ms": round(ms, 3), "box_cells": box, "box_gcups": round(box / (ms * 1e-3) / 1e9, 2),
             "kept": int(got[:, 3].sum()), "pairs": ps.n_pairs, "steps": steps,
             "thresholds": "identity >= 0.300, both coverages >= 0.700",
             "parity_sample": "%d/%d equal to the oracle" % (n_ok, len(sample)),
+            "coverage_first": {"ms": round(ms_cf, 3), "swept": int((got2[:, 1] >= 0).sum()),
+                               "keep_flags_equal": same_keep},
             "oracle_cpu": {"box_gcups": round(sample_cells / cpu_s / 1e9, 4), "cores": 1, "kind": "oracle",
                            "sample": "%d random pairs, %d box cells, %.2f s" % (len(sample), sample_cells, cpu_s)}}
 

@@ -298,7 +298,10 @@ SW_API int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, i
  *
  * Sets, offsets and pairs as for sw_align_sets; out_dev receives n_pairs
  * records.  Asynchronous on `stream` like sw_align_sets; with SW_VALIDATE the
- * call synchronises and reports device-found errors.  Workspace: one scratch
+ * call synchronises and reports device-found errors.  With SW_COVERAGE_FIRST
+ * a pair whose coverage already misses the threshold is not swept: its
+ * record is {score, -1, -1, 0} (keep is 0 either way, so every keep flag is
+ * the same as without the flag).  Workspace: one scratch
  * row pair of 65,536 int64 per resident wave (4 GiB on a 256-CU GPU),
  * allocated on the first call on a stream and kept.
  *
@@ -307,6 +310,8 @@ SW_API int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, i
  * box whose best score differs from the aligned score: found on the device,
  * reported under SW_VALIDATE or by sw_check), SW_ECODE, SW_ENOMEM, SW_EDEVICE.
  */
+#define SW_COVERAGE_FIRST 16u /* sw_identity: skip the sweep of pairs that fail coverage */
+
 typedef struct {
     int32_t score;   /* best global score of the box (the aligned score) */
     int32_t matches; /* identical aligned pairs */

@@ -30,6 +30,7 @@ PLAIN = 1
 VALIDATE = 2
 NO_GRAPH = 4
 TIMED = 8
+COVERAGE_FIRST = 16
 
 # every function the C header declares
 EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_check", "sw_timing_read",

@@ -31,6 +31,7 @@ struct IdentArgs {
     int32_t* err;           // device error bits (kErr*)
     int32_t go, ge;
     int32_t ani_permille, cov_permille;
+    int32_t coverage_first;  // skip pairs whose coverage fails
 };
 
 hipError_t launch_identity(const IdentArgs& a, int blocks, hipStream_t stream);

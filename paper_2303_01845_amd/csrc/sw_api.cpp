@@ -793,7 +793,7 @@ int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
                 sw_identity_result* out_dev, void* stream_, uint32_t flags)
 {
     if (!scoring || n_pairs < 0 || n_q < 0 || n_r < 0) return SW_EINVAL;
-    if (flags & ~SW_VALIDATE) return SW_EINVAL;
+    if (flags & ~(SW_VALIDATE | SW_COVERAGE_FIRST)) return SW_EINVAL;
     if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
         scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
         return SW_EINVAL;
@@ -860,6 +860,7 @@ int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     a.ge = scoring->gap_extend;
     a.ani_permille = ani_permille;
     a.cov_permille = cov_permille;
+    a.coverage_first = (flags & SW_COVERAGE_FIRST) ? 1 : 0;
     HIP_TRY(hipMemsetAsync(w.ident_next, 0, sizeof(int32_t), stream), "clear counter");
     HIP_TRY(launch_identity(a, blocks, stream), "identity launch");
     if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);

@@ -122,6 +122,15 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
             continue;
         }
         const int M = res.q_end - res.q_start + 1, N = res.r_end - res.r_start + 1;
+        const bool covered = (1000 * (int64_t)M >= (int64_t)a.cov_permille * m) &&
+                             (1000 * (int64_t)N >= (int64_t)a.cov_permille * n);
+        if (a.coverage_first && !covered) {  // cannot be kept: no sweep
+            rec.score = res.score;
+            rec.matches = -1;
+            rec.columns = -1;
+            if (lane == 0) a.out[k] = rec;
+            continue;
+        }
         const int64_t Q0 = qb + res.q_start, R0 = rb + res.r_start;
         const int n_strips = (M + 63) / 64;
         int64_t fin = kNegKey;
@@ -217,9 +226,7 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
                 rec.score = (int32_t)(fin >> kScoreShift);
                 rec.matches = (int32_t)((fin >> kMatchShift) & kFieldMask);
                 rec.columns = (int32_t)(kFieldMask - (fin & kFieldMask));
-                rec.keep = (1000 * (int64_t)rec.matches >= (int64_t)a.ani_permille * rec.columns) &&
-                           (1000 * (int64_t)M >= (int64_t)a.cov_permille * m) &&
-                           (1000 * (int64_t)N >= (int64_t)a.cov_permille * n);
+                rec.keep = (1000 * (int64_t)rec.matches >= (int64_t)a.ani_permille * rec.columns) && covered;
             }
             if (rec.score != res.score) bad_box = true;
             a.out[k] = rec;

@@ -138,6 +138,14 @@ def test_block_workload_full_size_sampled(sw):
     got = sw.identity(b.packed, b.offsets, b.packed, b.offsets, pairs, aligned, flags=sw.VALIDATE).cpu().numpy()
     a = aligned.cpu().numpy()
     say("block: %d pairs, %d kept" % (len(got), int(got[:, 3].sum())))
+    # coverage first: the same keep flags; swept pairs unchanged, the others -1
+    cf = sw.identity(b.packed, b.offsets, b.packed, b.offsets, pairs, aligned,
+                     flags=sw.VALIDATE | sw.COVERAGE_FIRST).cpu().numpy()
+    assert np.array_equal(cf[:, 3], got[:, 3]) and np.array_equal(cf[:, 0], got[:, 0])
+    swept = cf[:, 1] >= 0
+    assert np.array_equal(cf[swept], got[swept])
+    assert (cf[~swept, 1:3] == -1).all() and (got[~swept & (a[:, 0] > 0), 3] == 0).all()
+    say("block: coverage-first sweeps %d of %d pairs" % (int(swept.sum()), len(cf)))
     pos = a[:, 0] > 0
     assert (got[pos, 0] == a[pos, 0]).all() and (got[~pos] == 0).all()
     assert (got[:, 1] <= got[:, 2]).all()

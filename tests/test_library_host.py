@@ -140,6 +140,7 @@ def test_identity_argument_checks_precede_device_use():
     assert _identity_raw(ani=-1) == sw.SW_EINVAL
     assert _identity_raw(cov=1001) == sw.SW_EINVAL
     assert _identity_raw(flags=sw.PLAIN) == sw.SW_EINVAL
+    assert _identity_raw(flags=sw.TIMED) == sw.SW_EINVAL
     assert _identity_raw(n_pairs=-1) == sw.SW_EINVAL
     assert _identity_raw(null=True) == sw.SW_EINVAL
     assert _identity_raw(n_pairs=1 << 31) == sw.SW_ERANGE
