@@ -11,9 +11,11 @@
 // columns, and reports its matches and columns.
 //
 // One wave per pair, pairs handed out by a counter.  The box is swept in
-// strips of 64 rows: lane l owns row 64 s + l and at step t computes column
-// t - l, so the cell above and the one above-left come from lane l-1's
-// previous two steps by lane shuffles.  The strip's bottom row (H and F) goes
+// strips of 128 rows: lane l owns rows 128 s + 2l and 128 s + 2l + 1 and at
+// step t computes column t - l of both, so the cells above its first row come
+// from lane l-1's previous two steps by lane shuffles, and its second row
+// reads its first in registers (two cells per step share the shuffles and
+// loop overhead).  The strip's bottom row (H and F) goes
 // to the wave's scratch row in global memory for the next strip; lane 0 reads
 // it 64 columns at a time, one chunk ahead, as it reads the reference codes.
 //
@@ -37,6 +39,7 @@ constexpr int kScoreShift = 40;
 constexpr int kMatchShift = 20;
 constexpr int64_t kFieldMask = (int64_t(1) << 20) - 1;
 constexpr int64_t kOriginKey = kFieldMask;  // score 0, no matches, no columns
+constexpr int kStripRows = 128;             // two rows per lane
 
 __device__ __forceinline__ uint32_t code_at(const uint32_t* __restrict__ nib, const uint32_t* __restrict__ hib,
                                             int64_t pos)
@@ -132,21 +135,26 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
             continue;
         }
         const int64_t Q0 = qb + res.q_start, R0 = rb + res.r_start;
-        const int n_strips = (M + 63) / 64;
+        const int n_strips = (M + kStripRows - 1) / kStripRows;
         int64_t fin = kNegKey;
         for (int st = 0; st < n_strips; ++st) {
-            const int i = st * 64 + lane;
-            const int rows = min(64, M - st * 64);
-            const bool row_ok = lane < rows;
-            uint32_t qc = row_ok ? code_at(qnib, qhib, Q0 + i) : 0u;
-            if (qc >= (uint32_t)kNumSym) {
+            // lane l owns rows i0 = base + 2l and i1 = i0 + 1 of the strip
+            const int base = st * kStripRows;
+            const int rows = min(kStripRows, M - base);
+            const int i0 = base + 2 * lane, i1 = i0 + 1;
+            const bool ok0 = 2 * lane < rows, ok1 = 2 * lane + 1 < rows;
+            uint32_t qc0 = ok0 ? code_at(qnib, qhib, Q0 + i0) : 0u;
+            uint32_t qc1 = ok1 ? code_at(qnib, qhib, Q0 + i1) : 0u;
+            if (qc0 >= (uint32_t)kNumSym || qc1 >= (uint32_t)kNumSym) {
                 bad_code = true;
-                qc = 0;
+                qc0 = qc0 < (uint32_t)kNumSym ? qc0 : 0u;
+                qc1 = qc1 < (uint32_t)kNumSym ? qc1 : 0u;
             }
-            const int8_t* subrow = sub + qc * kNumSym;
-            int64_t E = kNegKey, Hleft = kNegKey;
+            const int8_t* sub0 = sub + qc0 * kNumSym;
+            const int8_t* sub1 = sub + qc1 * kNumSym;
+            int64_t E0 = kNegKey, E1 = kNegKey, Hleft0 = kNegKey, Hleft1 = kNegKey;
             int64_t diag_next = (lane == 0 && st == 0) ? kOriginKey : kNegKey;
-            int64_t outH = kNegKey, outF = kNegKey;
+            int64_t outH = kNegKey, outF = kNegKey;  // row i1, handed to lane l+1
             uint32_t rc_prev = 0;
             // reference codes and the row above, 64 columns per chunk, one
             // chunk ahead (reads past the box stay inside the padded buffer
@@ -161,7 +169,8 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
                 nxtH = Hrow[min(64 + lane, kIdentMaxCols - 1)];
                 nxtF = Frow[min(64 + lane, kIdentMaxCols - 1)];
             }
-            const int steps = N + rows - 1;
+            const int lanes_used = (rows + 1) / 2;
+            const int steps = N + lanes_used - 1;
             for (int t = 0; t < steps; ++t) {
                 if (t > 0 && (t & 63) == 0) {
                     cur = nxt;
@@ -193,26 +202,38 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
                 const int64_t diag = diag_next;
                 diag_next = upH;
                 const int j = t - lane;
-                if (row_ok && j >= 0 && j < N) {
+                if (ok0 && j >= 0 && j < N) {
                     uint32_t rcc = rc;
                     if (rcc >= (uint32_t)kNumSym) {
                         bad_code = true;
                         rcc = 0;
                     }
-                    const int64_t s = (int64_t)subrow[rcc];
-                    const int64_t step = (s << kScoreShift) + (qc == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
-                    const int64_t d = cut(diag + step);
-                    E = cut(kmax(E + GE, Hleft + GO));
-                    const int64_t F = cut(kmax(upF + GE, upH + GO));
-                    const int64_t H = kmax(d, kmax(E, F));
-                    Hleft = H;
-                    outH = H;
-                    outF = F;
+                    // row i0: up and above-left from lane l-1 (or the row above the strip)
+                    const int64_t s0 = (int64_t)sub0[rcc];
+                    const int64_t step0 = (s0 << kScoreShift) + (qc0 == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
+                    const int64_t d0 = cut(diag + step0);
+                    E0 = cut(kmax(E0 + GE, Hleft0 + GO));
+                    const int64_t F0 = cut(kmax(upF + GE, upH + GO));
+                    const int64_t H0 = kmax(d0, kmax(E0, F0));
+                    // row i1: up is row i0 of this column, above-left row i0 of the last one
+                    const int64_t s1 = (int64_t)sub1[rcc];
+                    const int64_t step1 = (s1 << kScoreShift) + (qc1 == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
+                    const int64_t d1 = cut(Hleft0 + step1);
+                    E1 = cut(kmax(E1 + GE, Hleft1 + GO));
+                    const int64_t F1 = cut(kmax(F0 + GE, H0 + GO));
+                    const int64_t H1 = kmax(d1, kmax(E1, F1));
+                    Hleft0 = H0;
+                    Hleft1 = H1;
+                    outH = H1;
+                    outF = F1;
                     if (lane == 63 && st + 1 < n_strips) {
-                        Hrow[j] = H;
-                        Frow[j] = F;
+                        Hrow[j] = H1;
+                        Frow[j] = F1;
                     }
-                    if (i == M - 1 && j == N - 1) fin = H;
+                    if (j == N - 1) {
+                        if (i0 == M - 1) fin = H0;
+                        if (ok1 && i1 == M - 1) fin = H1;
+                    }
                 } else {
                     outH = kNegKey;
                     outF = kNegKey;
@@ -221,7 +242,7 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
             // the strip's bottom row is in memory before the next strip reads it
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
         }
-        if (lane == ((M - 1) & 63)) {
+        if (lane == (((M - 1) % kStripRows) >> 1)) {
             if (fin >= 0) {
                 rec.score = (int32_t)(fin >> kScoreShift);
                 rec.matches = (int32_t)((fin >> kMatchShift) & kFieldMask);
