@@ -11,11 +11,11 @@
 // columns, and reports its matches and columns.
 //
 // One wave per pair, pairs handed out by a counter.  The box is swept in
-// strips of 128 rows: lane l owns rows 128 s + 2l and 128 s + 2l + 1 and at
-// step t computes column t - l of both, so the cells above its first row come
-// from lane l-1's previous two steps by lane shuffles, and its second row
-// reads its first in registers (two cells per step share the shuffles and
-// loop overhead).  The strip's bottom row (H and F) goes
+// strips of 64 R rows (R rows per lane): lane l owns rows 64 R s + R l ..
+// + R - 1 and at step t computes column t - l of all of them, so the cells
+// above its first row come from lane l-1's previous two steps by lane
+// shuffles, and each further row reads the one above it in registers (R
+// cells per step share the shuffles and the loop overhead).  The strip's bottom row (H and F) goes
 // to the wave's scratch row in global memory for the next strip; lane 0 reads
 // it 64 columns at a time, one chunk ahead, as it reads the reference codes.
 //
@@ -39,7 +39,8 @@ constexpr int kScoreShift = 40;
 constexpr int kMatchShift = 20;
 constexpr int64_t kFieldMask = (int64_t(1) << 20) - 1;
 constexpr int64_t kOriginKey = kFieldMask;  // score 0, no matches, no columns
-constexpr int kStripRows = 128;             // two rows per lane
+constexpr int kRowsPerLane = 4;
+constexpr int kStripRows = 64 * kRowsPerLane;
 
 __device__ __forceinline__ uint32_t code_at(const uint32_t* __restrict__ nib, const uint32_t* __restrict__ hib,
                                             int64_t pos)
@@ -138,23 +139,28 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
         const int n_strips = (M + kStripRows - 1) / kStripRows;
         int64_t fin = kNegKey;
         for (int st = 0; st < n_strips; ++st) {
-            // lane l owns rows i0 = base + 2l and i1 = i0 + 1 of the strip
+            // lane l owns rows i0 .. i0 + kRowsPerLane - 1 of the strip
             const int base = st * kStripRows;
             const int rows = min(kStripRows, M - base);
-            const int i0 = base + 2 * lane, i1 = i0 + 1;
-            const bool ok0 = 2 * lane < rows, ok1 = 2 * lane + 1 < rows;
-            uint32_t qc0 = ok0 ? code_at(qnib, qhib, Q0 + i0) : 0u;
-            uint32_t qc1 = ok1 ? code_at(qnib, qhib, Q0 + i1) : 0u;
-            if (qc0 >= (uint32_t)kNumSym || qc1 >= (uint32_t)kNumSym) {
-                bad_code = true;
-                qc0 = qc0 < (uint32_t)kNumSym ? qc0 : 0u;
-                qc1 = qc1 < (uint32_t)kNumSym ? qc1 : 0u;
+            const int i0 = base + kRowsPerLane * lane;
+            const bool ok0 = kRowsPerLane * lane < rows;
+            const int8_t* subr[kRowsPerLane];
+            uint32_t qcr[kRowsPerLane];
+            int64_t E[kRowsPerLane], Hleft[kRowsPerLane];
+#pragma unroll
+            for (int r = 0; r < kRowsPerLane; ++r) {
+                uint32_t qc = kRowsPerLane * lane + r < rows ? code_at(qnib, qhib, Q0 + i0 + r) : 0u;
+                if (qc >= (uint32_t)kNumSym) {
+                    bad_code = true;
+                    qc = 0;
+                }
+                qcr[r] = qc;
+                subr[r] = sub + qc * kNumSym;
+                E[r] = kNegKey;
+                Hleft[r] = kNegKey;
             }
-            const int8_t* sub0 = sub + qc0 * kNumSym;
-            const int8_t* sub1 = sub + qc1 * kNumSym;
-            int64_t E0 = kNegKey, E1 = kNegKey, Hleft0 = kNegKey, Hleft1 = kNegKey;
             int64_t diag_next = (lane == 0 && st == 0) ? kOriginKey : kNegKey;
-            int64_t outH = kNegKey, outF = kNegKey;  // row i1, handed to lane l+1
+            int64_t outH = kNegKey, outF = kNegKey;  // the lane's last row, handed to lane l+1
             uint32_t rc_prev = 0;
             // reference codes and the row above, 64 columns per chunk, one
             // chunk ahead (reads past the box stay inside the padded buffer
@@ -169,7 +175,7 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
                 nxtH = Hrow[min(64 + lane, kIdentMaxCols - 1)];
                 nxtF = Frow[min(64 + lane, kIdentMaxCols - 1)];
             }
-            const int lanes_used = (rows + 1) / 2;
+            const int lanes_used = (rows + kRowsPerLane - 1) / kRowsPerLane;
             const int steps = N + lanes_used - 1;
             for (int t = 0; t < steps; ++t) {
                 if (t > 0 && (t & 63) == 0) {
@@ -208,31 +214,28 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
                         bad_code = true;
                         rcc = 0;
                     }
-                    // row i0: up and above-left from lane l-1 (or the row above the strip)
-                    const int64_t s0 = (int64_t)sub0[rcc];
-                    const int64_t step0 = (s0 << kScoreShift) + (qc0 == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
-                    const int64_t d0 = cut(diag + step0);
-                    E0 = cut(kmax(E0 + GE, Hleft0 + GO));
-                    const int64_t F0 = cut(kmax(upF + GE, upH + GO));
-                    const int64_t H0 = kmax(d0, kmax(E0, F0));
-                    // row i1: up is row i0 of this column, above-left row i0 of the last one
-                    const int64_t s1 = (int64_t)sub1[rcc];
-                    const int64_t step1 = (s1 << kScoreShift) + (qc1 == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
-                    const int64_t d1 = cut(Hleft0 + step1);
-                    E1 = cut(kmax(E1 + GE, Hleft1 + GO));
-                    const int64_t F1 = cut(kmax(F0 + GE, H0 + GO));
-                    const int64_t H1 = kmax(d1, kmax(E1, F1));
-                    Hleft0 = H0;
-                    Hleft1 = H1;
-                    outH = H1;
-                    outF = F1;
-                    if (lane == 63 && st + 1 < n_strips) {
-                        Hrow[j] = H1;
-                        Frow[j] = F1;
+                    // row by row down the lane: the row above is the one just
+                    // computed, the above-left cell its value one column back
+                    int64_t dg = diag;
+#pragma unroll
+                    for (int r = 0; r < kRowsPerLane; ++r) {
+                        const int64_t sc = (int64_t)subr[r][rcc];
+                        const int64_t step = (sc << kScoreShift) + (qcr[r] == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
+                        const int64_t d = cut(dg + step);
+                        E[r] = cut(kmax(E[r] + GE, Hleft[r] + GO));
+                        const int64_t F = cut(kmax(upF + GE, upH + GO));
+                        const int64_t H = kmax(d, kmax(E[r], F));
+                        dg = Hleft[r];
+                        Hleft[r] = H;
+                        upH = H;
+                        upF = F;
+                        if (j == N - 1 && i0 + r == M - 1) fin = H;
                     }
-                    if (j == N - 1) {
-                        if (i0 == M - 1) fin = H0;
-                        if (ok1 && i1 == M - 1) fin = H1;
+                    outH = upH;
+                    outF = upF;
+                    if (lane == 63 && st + 1 < n_strips) {
+                        Hrow[j] = upH;
+                        Frow[j] = upF;
                     }
                 } else {
                     outH = kNegKey;
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
             // the strip's bottom row is in memory before the next strip reads it
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
         }
-        if (lane == (((M - 1) % kStripRows) >> 1)) {
+        if (lane == ((M - 1) % kStripRows) / kRowsPerLane) {
             if (fin >= 0) {
                 rec.score = (int32_t)(fin >> kScoreShift);
                 rec.matches = (int32_t)((fin >> kMatchShift) & kFieldMask);
