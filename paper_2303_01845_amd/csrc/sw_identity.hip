@@ -15,7 +15,9 @@
 // + R - 1 and at step t computes column t - l of all of them, so the cells
 // above its first row come from lane l-1's previous two steps by lane
 // shuffles, and each further row reads the one above it in registers (R
-// cells per step share the shuffles and the loop overhead).  The strip's bottom row (H and F) goes
+// cells per step share the shuffles and the loop overhead).  R is 1, 2 or 4,
+// the smallest that covers the box in one strip, else 4: a strip costs the
+// wave about N steps whatever its height.  The strip's bottom row (H and F) goes
 // to the wave's scratch row in global memory for the next strip; lane 0 reads
 // it 64 columns at a time, one chunk ahead, as it reads the reference codes.
 //
@@ -39,8 +41,6 @@ constexpr int kScoreShift = 40;
 constexpr int kMatchShift = 20;
 constexpr int64_t kFieldMask = (int64_t(1) << 20) - 1;
 constexpr int64_t kOriginKey = kFieldMask;  // score 0, no matches, no columns
-constexpr int kRowsPerLane = 4;
-constexpr int kStripRows = 64 * kRowsPerLane;
 
 __device__ __forceinline__ uint32_t code_at(const uint32_t* __restrict__ nib, const uint32_t* __restrict__ hib,
                                             int64_t pos)
@@ -76,7 +76,128 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int src)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs a)
+// Sweep one box in strips of 64 R rows (R rows per lane) and return the key
+// of its last cell on the lane that owns it (kNegKey on the others).
+template <int R>
+__device__ __forceinline__ int64_t sweep_box(const int8_t* sub, int64_t* Hrow, int64_t* Frow,
+                                             const uint32_t* qnib, const uint32_t* qhib, const uint32_t* rnib,
+                                             const uint32_t* rhib, int64_t GO, int64_t GE, int M, int N,
+                                             int64_t Q0, int64_t R0, int lane, bool& bad_code)
+{
+    constexpr int kStrip = 64 * R;
+    const int n_strips = (M + kStrip - 1) / kStrip;
+    int64_t fin = kNegKey;
+    for (int st = 0; st < n_strips; ++st) {
+        // lane l owns rows i0 .. i0 + R - 1 of the strip
+        const int base = st * kStrip;
+        const int rows = min(kStrip, M - base);
+        const int i0 = base + R * lane;
+        const bool ok0 = R * lane < rows;
+        const int8_t* subr[R];
+        uint32_t qcr[R];
+        int64_t E[R], Hleft[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uint32_t qc = R * lane + r < rows ? code_at(qnib, qhib, Q0 + i0 + r) : 0u;
+            if (qc >= (uint32_t)kNumSym) {
+                bad_code = true;
+                qc = 0;
+            }
+            qcr[r] = qc;
+            subr[r] = sub + qc * kNumSym;
+            E[r] = kNegKey;
+            Hleft[r] = kNegKey;
+        }
+        int64_t diag_next = (lane == 0 && st == 0) ? kOriginKey : kNegKey;
+        int64_t outH = kNegKey, outF = kNegKey;  // the lane's last row, handed to lane l+1
+        uint32_t rc_prev = 0;
+        // reference codes and the row above, 64 columns per chunk, one
+        // chunk ahead (reads past the box stay inside the padded buffer
+        // and the wave's scratch row; their values are never used)
+        uint32_t cur = code_at(rnib, rhib, R0 + lane);
+        uint32_t nxt = code_at(rnib, rhib, R0 + 64 + lane);
+        const bool above = st > 0;
+        int64_t curH = kNegKey, curF = kNegKey, nxtH = kNegKey, nxtF = kNegKey;
+        if (above) {
+            curH = Hrow[lane];
+            curF = Frow[lane];
+            nxtH = Hrow[min(64 + lane, kIdentMaxCols - 1)];
+            nxtF = Frow[min(64 + lane, kIdentMaxCols - 1)];
+        }
+        const int lanes_used = (rows + R - 1) / R;
+        const int steps = N + lanes_used - 1;
+        for (int t = 0; t < steps; ++t) {
+            if (t > 0 && (t & 63) == 0) {
+                cur = nxt;
+                nxt = code_at(rnib, rhib, R0 + t + 64 + lane);
+                if (above) {
+                    curH = nxtH;
+                    curF = nxtF;
+                    const int c = min(t + 64 + lane, kIdentMaxCols - 1);
+                    nxtH = Hrow[c];
+                    nxtF = Frow[c];
+                }
+            }
+            // lane 0's inputs (the new column's code, the row above) are
+            // read from one lane of the chunk; every other lane takes its
+            // left neighbour's values of the previous step
+            const int src = t & 63;
+            const uint32_t rc_new = readlane32(cur, src);
+            const uint32_t rc_up = (uint32_t)__shfl_up((int)rc_prev, 1, 64);
+            const uint32_t rc = lane == 0 ? rc_new : rc_up;
+            rc_prev = rc;
+            int64_t upH = shfl_up64(outH);
+            int64_t upF = shfl_up64(outF);
+            const int64_t topH = readlane64(curH, src);
+            const int64_t topF = readlane64(curF, src);
+            if (lane == 0) {
+                upH = (above && t < N) ? topH : kNegKey;
+                upF = (above && t < N) ? topF : kNegKey;
+            }
+            const int64_t diag = diag_next;
+            diag_next = upH;
+            const int j = t - lane;
+            if (ok0 && j >= 0 && j < N) {
+                uint32_t rcc = rc;
+                if (rcc >= (uint32_t)kNumSym) {
+                    bad_code = true;
+                    rcc = 0;
+                }
+                // row by row down the lane: the row above is the one just
+                // computed, the above-left cell its value one column back
+                int64_t dg = diag;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t sc = (int64_t)subr[r][rcc];
+                    const int64_t step = (sc << kScoreShift) + (qcr[r] == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
+                    const int64_t d = cut(dg + step);
+                    E[r] = cut(kmax(E[r] + GE, Hleft[r] + GO));
+                    const int64_t F = cut(kmax(upF + GE, upH + GO));
+                    const int64_t H = kmax(d, kmax(E[r], F));
+                    dg = Hleft[r];
+                    Hleft[r] = H;
+                    upH = H;
+                    upF = F;
+                    if (j == N - 1 && i0 + r == M - 1) fin = H;
+                }
+                outH = upH;
+                outF = upF;
+                if (lane == 63 && st + 1 < n_strips) {
+                    Hrow[j] = upH;
+                    Frow[j] = upF;
+                }
+            } else {
+                outH = kNegKey;
+                outF = kNegKey;
+            }
+        }
+        // the strip's bottom row is in memory before the next strip reads it
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+    }
+    return fin;
+}
+
+__global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentArgs a)
 {
     __shared__ int8_t sub[kNumSym * kNumSym];
     for (int i = threadIdx.x; i < kNumSym * kNumSym; i += blockDim.x) sub[i] = a.subst[i];
@@ -136,116 +257,19 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock) k_identity(IdentArgs
             continue;
         }
         const int64_t Q0 = qb + res.q_start, R0 = rb + res.r_start;
-        const int n_strips = (M + kStripRows - 1) / kStripRows;
-        int64_t fin = kNegKey;
-        for (int st = 0; st < n_strips; ++st) {
-            // lane l owns rows i0 .. i0 + kRowsPerLane - 1 of the strip
-            const int base = st * kStripRows;
-            const int rows = min(kStripRows, M - base);
-            const int i0 = base + kRowsPerLane * lane;
-            const bool ok0 = kRowsPerLane * lane < rows;
-            const int8_t* subr[kRowsPerLane];
-            uint32_t qcr[kRowsPerLane];
-            int64_t E[kRowsPerLane], Hleft[kRowsPerLane];
-#pragma unroll
-            for (int r = 0; r < kRowsPerLane; ++r) {
-                uint32_t qc = kRowsPerLane * lane + r < rows ? code_at(qnib, qhib, Q0 + i0 + r) : 0u;
-                if (qc >= (uint32_t)kNumSym) {
-                    bad_code = true;
-                    qc = 0;
-                }
-                qcr[r] = qc;
-                subr[r] = sub + qc * kNumSym;
-                E[r] = kNegKey;
-                Hleft[r] = kNegKey;
-            }
-            int64_t diag_next = (lane == 0 && st == 0) ? kOriginKey : kNegKey;
-            int64_t outH = kNegKey, outF = kNegKey;  // the lane's last row, handed to lane l+1
-            uint32_t rc_prev = 0;
-            // reference codes and the row above, 64 columns per chunk, one
-            // chunk ahead (reads past the box stay inside the padded buffer
-            // and the wave's scratch row; their values are never used)
-            uint32_t cur = code_at(rnib, rhib, R0 + lane);
-            uint32_t nxt = code_at(rnib, rhib, R0 + 64 + lane);
-            const bool above = st > 0;
-            int64_t curH = kNegKey, curF = kNegKey, nxtH = kNegKey, nxtF = kNegKey;
-            if (above) {
-                curH = Hrow[lane];
-                curF = Frow[lane];
-                nxtH = Hrow[min(64 + lane, kIdentMaxCols - 1)];
-                nxtF = Frow[min(64 + lane, kIdentMaxCols - 1)];
-            }
-            const int lanes_used = (rows + kRowsPerLane - 1) / kRowsPerLane;
-            const int steps = N + lanes_used - 1;
-            for (int t = 0; t < steps; ++t) {
-                if (t > 0 && (t & 63) == 0) {
-                    cur = nxt;
-                    nxt = code_at(rnib, rhib, R0 + t + 64 + lane);
-                    if (above) {
-                        curH = nxtH;
-                        curF = nxtF;
-                        const int c = min(t + 64 + lane, kIdentMaxCols - 1);
-                        nxtH = Hrow[c];
-                        nxtF = Frow[c];
-                    }
-                }
-                // lane 0's inputs (the new column's code, the row above) are
-                // read from one lane of the chunk; every other lane takes its
-                // left neighbour's values of the previous step
-                const int src = t & 63;
-                const uint32_t rc_new = readlane32(cur, src);
-                const uint32_t rc_up = (uint32_t)__shfl_up((int)rc_prev, 1, 64);
-                const uint32_t rc = lane == 0 ? rc_new : rc_up;
-                rc_prev = rc;
-                int64_t upH = shfl_up64(outH);
-                int64_t upF = shfl_up64(outF);
-                const int64_t topH = readlane64(curH, src);
-                const int64_t topF = readlane64(curF, src);
-                if (lane == 0) {
-                    upH = (above && t < N) ? topH : kNegKey;
-                    upF = (above && t < N) ? topF : kNegKey;
-                }
-                const int64_t diag = diag_next;
-                diag_next = upH;
-                const int j = t - lane;
-                if (ok0 && j >= 0 && j < N) {
-                    uint32_t rcc = rc;
-                    if (rcc >= (uint32_t)kNumSym) {
-                        bad_code = true;
-                        rcc = 0;
-                    }
-                    // row by row down the lane: the row above is the one just
-                    // computed, the above-left cell its value one column back
-                    int64_t dg = diag;
-#pragma unroll
-                    for (int r = 0; r < kRowsPerLane; ++r) {
-                        const int64_t sc = (int64_t)subr[r][rcc];
-                        const int64_t step = (sc << kScoreShift) + (qcr[r] == rcc ? (int64_t(1) << kMatchShift) : 0) - 1;
-                        const int64_t d = cut(dg + step);
-                        E[r] = cut(kmax(E[r] + GE, Hleft[r] + GO));
-                        const int64_t F = cut(kmax(upF + GE, upH + GO));
-                        const int64_t H = kmax(d, kmax(E[r], F));
-                        dg = Hleft[r];
-                        Hleft[r] = H;
-                        upH = H;
-                        upF = F;
-                        if (j == N - 1 && i0 + r == M - 1) fin = H;
-                    }
-                    outH = upH;
-                    outF = upF;
-                    if (lane == 63 && st + 1 < n_strips) {
-                        Hrow[j] = upH;
-                        Frow[j] = upF;
-                    }
-                } else {
-                    outH = kNegKey;
-                    outF = kNegKey;
-                }
-            }
-            // the strip's bottom row is in memory before the next strip reads it
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        int64_t fin;
+        int fin_lane;
+        if (M <= 64) {
+            fin = sweep_box<1>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
+            fin_lane = M - 1;
+        } else if (M <= 128) {
+            fin = sweep_box<2>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
+            fin_lane = (M - 1) / 2;
+        } else {
+            fin = sweep_box<4>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
+            fin_lane = ((M - 1) % 256) / 4;
         }
-        if (lane == ((M - 1) % kStripRows) / kRowsPerLane) {
+        if (lane == fin_lane) {
             if (fin >= 0) {
                 rec.score = (int32_t)(fin >> kScoreShift);
                 rec.matches = (int32_t)((fin >> kMatchShift) & kFieldMask);
