@@ -80,11 +80,16 @@ typedef struct {
 
 /*
  * Bytes a packed buffer needs for n_residues residues (header, two residue
- * planes, guard and slack).
+ * planes, guard and slack).  The paper's alignment driver packs the sequences
+ * before handing them to the GPU kernels (section "Software stack and
+ * parallelism"); this is the size of that packed form.
  */
 SW_API size_t sw_packed_bytes(int64_t n_residues);
 
 /*
+ * Packing step of the alignment driver (section "Software stack and
+ * parallelism": the driver between the application and the kernels packs the
+ * data and moves it to the GPU).
  * Encode a concatenated ASCII buffer of n_residues residues (device memory)
  * into the library's packed 5-bit form: a 4-bit plane (8 residues per 32-bit
  * word) followed by a 1-bit plane (32 residues per word), the layout being
@@ -102,6 +107,9 @@ SW_API int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, 
             void* stream);
 
 /*
+ * Batch alignment of candidate pairs, stage (ii) of the paper's pipeline
+ * (section "Protein similarity search pipeline"), over the whole m x n matrix
+ * of every pair (section "Load balancing techniques").
  * Align n_pairs candidate pairs.
  *   packed_dev    buffer written by sw_pack (16-byte aligned)
  *   offsets_dev   int64[n_seqs + 1]: sequence k is residues offsets[k] ..
@@ -127,12 +135,17 @@ SW_API int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, in
                    sw_result* out_dev, void* stream, uint32_t flags);
 
 /*
+ * The search of one sequence set against another (section "Overview of the
+ * Problem": queries against references, or a set against itself).
  * Align pairs drawn from two sequence sets, each packed by sw_pack into its
  * own buffer (for instance a query batch against a reference set that stays
  * resident in HBM).  pairs_dev[2k] indexes the query set (n_q sequences,
  * q_offsets_dev int64[n_q + 1]) and pairs_dev[2k+1] the reference set.
  * Results, flags and errors as for sw_batch_align, which is this call with
- * both sets equal.
+ * both sets equal.  The device workspace (sort tables, the pair permutation
+ * and one boundary-row slot per resident block, about 3 GiB on a 256-CU GPU)
+ * belongs to the library: allocated on the first call on a stream, grown to
+ * the largest call and kept.
  */
 SW_API int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
                          const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
@@ -140,12 +153,48 @@ SW_API int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev,
                          sw_result* out_dev, void* stream, uint32_t flags);
 
 /*
+ * Device workspace of a caller-owned alignment call (the driver role of
+ * section "Software stack and parallelism", with the memory left to the
+ * caller).  *bytes (host) receives the size that lets sw_align_sets_ws run
+ * n_pairs pairs on the full persistent grid of the current tuning, with
+ * boundary-row slots large enough that every pair whose reference holds up
+ * to max_len residues takes the fastest whole-wave form.  Smaller buffers
+ * still work (see sw_align_sets_ws).
+ * Errors: SW_EINVAL (null pointer, negative argument), SW_ERANGE (max_len
+ * above SW_MAX_SEQ_LEN, n_pairs of 2^31 - 64 or more), SW_EDEVICE.
+ */
+SW_API int sw_workspace_size(int64_t n_pairs, int64_t max_len, size_t* bytes);
+
+/*
+ * sw_align_sets with the device workspace in workspace_dev (device memory,
+ * 256-byte aligned, workspace_bytes long, owned by the caller; the library
+ * allocates no device memory for the call and keeps no pointer into the
+ * buffer after the enqueued work completes).  The buffer holds the sort
+ * tables, the two pair arrays and then as many boundary-row slots of at
+ * least 768 KiB as fit, up to one per resident block of the persistent grid:
+ * a buffer below the sw_workspace_size figure runs a smaller grid (fewer
+ * blocks at once, same results).  Two calls in flight at the same time must
+ * not share a buffer.  Arguments, results and flags as for sw_align_sets.
+ * Errors: as sw_align_sets, plus SW_EINVAL (workspace_dev NULL or not
+ * 256-byte aligned) and SW_ENOMEM (not even one slot fits).
+ */
+SW_API int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                            const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
+                            const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring,
+                            sw_result* out_dev, void* workspace_dev, size_t workspace_bytes, void* stream,
+                            uint32_t flags);
+
+/*
+ * Error check of the driver (section "Software stack and parallelism"): the
+ * kernels record invalid input in a device word instead of stopping.
  * Synchronise `stream`, then return and clear the device-detected errors
  * (SW_ERANGE, SW_ECODE) raised by earlier calls on the current device.
  */
 SW_API int sw_check(void* stream);
 
 /*
+ * Timers of the kernels (section "How Performance Was Measured": cell updates
+ * per second use the time of the alignment kernel alone).
  * Device time of the alignment kernels of the calls made with SW_TIMED on
  * `stream` since the previous read: the two persistent launches of each
  * persistent call (forward passes, then start passes; the sorting kernels
@@ -160,7 +209,9 @@ SW_API int sw_check(void* stream);
 SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
 
 /*
- * The same read, split by pass: *forward_ms sums the forward launches of
+ * The same read, split by pass (the paper's cell-update rate counts the
+ * forward scoring time only, section "How Performance Was Measured"):
+ * *forward_ms sums the forward launches of
  * persistent calls (and the whole launch series of SW_PLAIN calls, which run
  * both passes together), *start_ms the start-pass launches.  Synchronises
  * `stream`, forgets the timed calls.  Errors: SW_EINVAL, SW_EDEVICE.
@@ -168,7 +219,9 @@ SW_API int sw_timing_read(void* stream, double* kernel_ms, int64_t* calls);
 SW_API int sw_timing_read_passes(void* stream, double* forward_ms, double* start_ms, int64_t* calls);
 
 /*
- * Kernel shape used by later calls on the current device.  rows_per_lane is
+ * Kernel shape (the split of work between lanes, the paper's inter- and
+ * intra-task parallelism of section "Software stack and parallelism"), used
+ * by later calls on the current device.  rows_per_lane is
  * the number of query rows each lane keeps in registers (8 or 16);
  * inter_max_len is the longest pair (max of both lengths, 64..1024, at most
  * 64 rows_per_lane) that is aligned one pair per lane; longer pairs up to
@@ -209,6 +262,7 @@ SW_API int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64
                        sw_result* out_dev, void* stream, int32_t reps, sw_tuning* chosen, float* best_ms);
 
 /*
+ * The scoring matrix (the paper does not name one; BLOSUM62 is used).
  * The library's substitution matrix in the alphabet order above
  * (scores[24*q + r], query symbol q, reference symbol r) and the alphabet
  * itself (25 bytes including the terminating zero).  Host memory.
@@ -344,13 +398,19 @@ SW_API int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, i
  */
 typedef struct sw_server sw_server;
 
-/* Errors: SW_EINVAL (bad argument or scoring), SW_ENOMEM (arena allocation),
+/* A resident reference set and its request loop: the paper's search aligns
+ * query batches against a reference set one block at a time (sections
+ * "Blocked 2D Sparse SUMMA" and "Pre-blocking": the next batch is made ready
+ * while the current one aligns).
+ * Errors: SW_EINVAL (bad argument or scoring), SW_ENOMEM (arena allocation),
  * SW_EDEVICE. */
 SW_API int sw_server_create(const void* refs_packed_dev, const int64_t* ref_offsets_dev, int64_t n_refs,
                             const sw_scoring* scoring, size_t hbm_budget_bytes, int max_slots,
                             sw_server** server);
 
-/* Submit n_q query sequences (host ASCII, host int64 offsets[n_q + 1] with
+/* Admission of one query batch with its candidate list (the pairs stage (i)
+ * of section "Protein similarity search pipeline" discovered).
+ * Submit n_q query sequences (host ASCII, host int64 offsets[n_q + 1] with
  * offsets[0] == 0) with n_cand candidate pairs (host int32 [query index within
  * the request, reference index]).  On SW_OK *ticket identifies the request and
  * out_host (host, n_cand results) is written when the request completes
@@ -362,24 +422,33 @@ SW_API int sw_server_create(const void* refs_packed_dev, const int64_t* ref_offs
 SW_API int sw_server_submit(sw_server* server, const char* q_ascii, const int64_t* q_offsets, int64_t n_q,
                             const int32_t* cand, int64_t n_cand, sw_result* out_host, uint64_t* ticket);
 
-/* SW_OK once the request is complete (results copied, resources freed; the
+/* Completion of a request (its alignments, stage (ii) of section "Protein
+ * similarity search pipeline").
+ * SW_OK once the request is complete (results copied, resources freed; the
  * ticket is then retired), SW_EAGAIN while it waits or runs, SW_EINVAL for an
  * unknown ticket; a launch that failed returns its error (SW_EDEVICE,
  * SW_ENOMEM) for each of its requests. */
 SW_API int sw_server_poll(sw_server* server, uint64_t ticket);
 
-/* Poll until complete or until timeout_us elapses (SW_ETIMEOUT); a negative
+/* Bounded wait for a request (as sw_server_poll, section "Protein similarity
+ * search pipeline" stage (ii)).
+ * Poll until complete or until timeout_us elapses (SW_ETIMEOUT); a negative
  * timeout waits without limit. */
 SW_API int sw_server_wait(sw_server* server, uint64_t ticket, int64_t timeout_us);
 
-/* Requests admitted and not complete, budget bytes they hold and the budget
+/* Memory held by requests in flight (the paper bounds the memory of the
+ * blocks in flight, section "Pre-blocking": extra memory for the next block).
+ * Requests admitted and not complete, budget bytes they hold and the budget
  * (any pointer may be NULL). */
 SW_API int sw_server_stats(sw_server* server, int64_t* inflight, int64_t* bytes_in_use, int64_t* budget);
 
-/* Arena bytes a request of this size needs (0 for negative arguments). */
+/* Admission size of a request (section "Pre-blocking": memory of a block in
+ * flight).  Arena bytes a request of this size needs (0 for negative
+ * arguments). */
 SW_API size_t sw_server_request_bytes(int64_t n_residues, int64_t n_q, int64_t n_cand);
 
-/* Wait for every request in flight, then free the server. */
+/* End of the request loop (section "Pre-blocking"): wait for every request
+ * in flight, then free the server. */
 SW_API int sw_server_destroy(sw_server* server);
 
 /* Text of a status code; never NULL. */

@@ -33,7 +33,8 @@ TIMED = 8
 COVERAGE_FIRST = 16
 
 # every function the C header declares
-EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_check", "sw_timing_read",
+EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_align_sets_ws",
+           "sw_workspace_size", "sw_check", "sw_timing_read",
            "sw_timing_read_passes", "sw_set_tuning",
            "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
            "sw_server_submit", "sw_server_poll", "sw_server_wait", "sw_server_stats",
@@ -87,6 +88,12 @@ def lib():
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+        L.sw_align_sets_ws.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                       ctypes.c_uint32]
+        L.sw_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
         L.sw_check.argtypes = [ctypes.c_void_p]
         L.sw_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64)]
@@ -197,6 +204,35 @@ def align_sets(q_packed, q_offsets, r_packed, r_offsets, pairs, gap_open: int = 
                                ctypes.c_void_p(pairs.data_ptr()), n_pairs, ctypes.byref(sc),
                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), int(flags)),
            "sw_align_sets")
+    return out
+
+
+def workspace_size(n_pairs: int, max_len: int = MAX_SEQ_LEN) -> int:
+    """Bytes of a caller-owned workspace for sw_align_sets_ws (full grid,
+    every pair up to ``max_len`` reference residues on the whole-wave scan)."""
+    b = ctypes.c_size_t()
+    _check(lib().sw_workspace_size(int(n_pairs), int(max_len), ctypes.byref(b)), "sw_workspace_size")
+    return int(b.value)
+
+
+def align_sets_ws(q_packed, q_offsets, r_packed, r_offsets, pairs, workspace, gap_open: int = 11,
+                  gap_extend: int = 1, flags: int = PERSISTENT, out=None, stream=None):
+    """align_sets with a caller-owned device workspace (a uint8 tensor,
+    256-byte aligned; see workspace_size)."""
+    import torch
+    n_pairs = int(pairs.shape[0]) if pairs.dim() == 2 else int(pairs.numel() // 2)
+    if out is None:
+        out = torch.empty((n_pairs, 5), dtype=torch.int32, device=pairs.device)
+    assert q_offsets.dtype == torch.int64 and r_offsets.dtype == torch.int64
+    assert pairs.dtype == torch.int32 and out.dtype == torch.int32 and pairs.is_contiguous()
+    sc = Scoring(0, int(gap_open), int(gap_extend))
+    _check(lib().sw_align_sets_ws(ctypes.c_void_p(q_packed.data_ptr()), ctypes.c_void_p(q_offsets.data_ptr()),
+                                  int(q_offsets.numel()) - 1, ctypes.c_void_p(r_packed.data_ptr()),
+                                  ctypes.c_void_p(r_offsets.data_ptr()), int(r_offsets.numel()) - 1,
+                                  ctypes.c_void_p(pairs.data_ptr()), n_pairs, ctypes.byref(sc),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                                  int(workspace.numel() * workspace.element_size()), _stream_ptr(stream),
+                                  int(flags)), "sw_align_sets_ws")
     return out
 
 

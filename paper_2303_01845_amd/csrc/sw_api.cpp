@@ -129,12 +129,14 @@ struct GraphKey {
     void* out;
     int R, inter_max, group8_max, group16_max, grid;
     int64_t slot_words;
+    const void* ws_base;  // device workspace the graphs read and write
     bool operator<(const GraphKey& o) const
     {
         return std::tie(q_packed, q_offsets, n_q, r_packed, r_offsets, n_r, pairs, n_pairs, go, ge, out, R,
-                        inter_max, group8_max, group16_max, grid, slot_words) <
+                        inter_max, group8_max, group16_max, grid, slot_words, ws_base) <
                std::tie(o.q_packed, o.q_offsets, o.n_q, o.r_packed, o.r_offsets, o.n_r, o.pairs, o.n_pairs, o.go,
-                        o.ge, o.out, o.R, o.inter_max, o.group8_max, o.group16_max, o.grid, o.slot_words);
+                        o.ge, o.out, o.R, o.inter_max, o.group8_max, o.group16_max, o.grid, o.slot_words,
+                        o.ws_base);
     }
 };
 
@@ -251,10 +253,10 @@ struct Device {
     int group8_max = kDefaultGroup8Max;
     int bpc_user = 0;  // 0: occupancy-derived
     Ordering ord;
-    int32_t* rank_cell_persistent = nullptr;
+    int32_t* rank_cell_persistent = nullptr;  // file-scope device arrays (device_statics)
     int32_t* rank_cell_plain = nullptr;
     int32_t* err = nullptr;
-    hipStream_t capture_stream = nullptr;
+    hipStream_t capture_stream = nullptr;     // created by the first graph capture
     std::map<hipStream_t, std::unique_ptr<Workspace>> ws;
 };
 
@@ -284,14 +286,17 @@ int get_device(Device** out)
     if (!slot) slot.reset(new Device());
     Device& d = *slot;
     if (!d.ready) {
+        // set-up allocates nothing: the per-device tables are file-scope
+        // device arrays, looked up with this device current
         d.id = id;
         HIP_TRY(hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, id), "device attributes");
         HIP_TRY(set_kernel_attributes(), "kernel attributes");
-        HIP_TRY(hipMalloc(&d.rank_cell_persistent, sizeof(int32_t) * kNumCells), "hipMalloc");
-        HIP_TRY(hipMalloc(&d.rank_cell_plain, sizeof(int32_t) * kNumCells), "hipMalloc");
-        HIP_TRY(hipMalloc(&d.err, sizeof(int32_t)), "hipMalloc");
+        DeviceStatics st{};
+        HIP_TRY(device_statics(&st), "hipGetSymbolAddress");
+        d.rank_cell_persistent = st.rank_cell_persistent;
+        d.rank_cell_plain = st.rank_cell_plain;
+        d.err = st.err;
         HIP_TRY(hipMemset(d.err, 0, sizeof(int32_t)), "hipMemset");
-        HIP_TRY(hipStreamCreateWithFlags(&d.capture_stream, hipStreamNonBlocking), "hipStreamCreate");
         int rc = upload_ordering(d);
         if (rc != SW_OK) return rc;
         d.ready = true;
@@ -321,18 +326,84 @@ int grow(T** p, int64_t count)
     return SW_OK;
 }
 
-int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, Workspace** out)
+// Host-side state of a stream (graphs, timing events, pinned buffers, the
+// other passes' tables); device arrays of the aligner are added on demand.
+int get_workspace(Device& d, hipStream_t stream, Workspace** out)
 {
     auto& slot = d.ws[stream];
     if (!slot) slot.reset(new Workspace());
-    Workspace& w = *slot;
+    *out = slot.get();
+    return SW_OK;
+}
+
+// The device arrays of one alignment call, wherever they live: the library's
+// own per-stream arrays, or one buffer the caller owns, carved the same way.
+struct WsView {
+    int32_t* pair_cell = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* cell_count = nullptr;
+    int32_t* rank_start = nullptr;
+    int32_t* counters = nullptr;
+    uint32_t* scratch = nullptr;
+    int64_t slot_words = 0;
+    int grid = 0;
+    const void* base = nullptr;
+};
+
+constexpr size_t kWsAlign = 256;
+size_t up_ws(size_t b) { return (b + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+// Bytes of a carved workspace before its boundary-row slots.
+size_t ws_head_bytes(int64_t n_pairs)
+{
+    const size_t np = (size_t)std::max<int64_t>(n_pairs, 1);
+    return up_ws(sizeof(int32_t) * kNumCells * kCellShards) + up_ws(sizeof(int32_t) * (kNumCells + 1)) +
+           up_ws(sizeof(int32_t) * kNumCounters) + 2 * up_ws(sizeof(int32_t) * np);
+}
+
+// Lay one call's arrays out in a buffer of `bytes`: the sort tables and the
+// two pair arrays, then as many boundary-row slots of at least slot_words()
+// as fit, up to max_grid (one per resident block of the persistent grid);
+// the slots share what is left, up to the size at which every pair takes the
+// whole-wave scan.  SW_ENOMEM if not even one slot fits.
+int carve_workspace(void* base, size_t bytes, int64_t n_pairs, int max_grid, WsView* v)
+{
+    const size_t head = ws_head_bytes(n_pairs);
+    const size_t min_slot = sizeof(uint32_t) * (size_t)slot_words();
+    if (bytes < head || bytes - head < min_slot || max_grid < 1) return SW_ENOMEM;
+    const size_t room = bytes - head;
+    const int grid = (int)std::min<size_t>((size_t)max_grid, room / min_slot);
+    int64_t sw = (int64_t)(room / (size_t)grid / sizeof(uint32_t)) & ~(int64_t)63;
+    sw = std::min(sw, slot_words_for(SW_MAX_SEQ_LEN));
+    char* p = static_cast<char*>(base);
+    auto take = [&](size_t b) {
+        char* q = p;
+        p += up_ws(b);
+        return reinterpret_cast<int32_t*>(q);
+    };
+    const size_t np = (size_t)std::max<int64_t>(n_pairs, 1);
+    v->cell_count = take(sizeof(int32_t) * kNumCells * kCellShards);
+    v->rank_start = take(sizeof(int32_t) * (kNumCells + 1));
+    v->counters = take(sizeof(int32_t) * kNumCounters);
+    v->pair_cell = take(sizeof(int32_t) * np);
+    v->perm = take(sizeof(int32_t) * np);
+    v->scratch = reinterpret_cast<uint32_t*>(p);
+    v->slot_words = sw;
+    v->grid = grid;
+    v->base = base;
+    return SW_OK;
+}
+
+// The library's own arrays for this stream: grown to the largest call and
+// kept; slots sized so that every pair takes the whole-wave scan.
+int library_workspace(Workspace& w, int64_t n_pairs, int grid, WsView* v)
+{
     bool changed = false;
     if (!w.cell_count) {
         int rc;
         if ((rc = grow(&w.cell_count, (int64_t)kNumCells * kCellShards)) || (rc = grow(&w.rank_start, kNumCells + 1)) ||
             (rc = grow(&w.counters, kNumCounters)))
             return rc;
-        HIP_TRY(hipHostMalloc((void**)&w.host_rank_start, sizeof(int32_t) * (kNumCells + 1)), "hipHostMalloc");
         changed = true;
     }
     if (n_pairs > w.pair_cap) {
@@ -342,22 +413,26 @@ int get_workspace(Device& d, hipStream_t stream, int64_t n_pairs, Workspace** ou
         w.pair_cap = cap;
         changed = true;
     }
-    if (changed) w.drop_graphs();
-    *out = &w;
-    return SW_OK;
-}
-
-// Scratch slots for `grid` blocks of `words` each (never shrinks).
-int ensure_scratch(Workspace& w, int64_t need)
-{
-    if (need <= w.scratch_words) return SW_OK;
-    int rc = grow(&w.scratch, need);
-    if (rc) {
-        w.scratch_words = 0;
-        return rc;
+    const int64_t sw = slot_words_for(SW_MAX_SEQ_LEN);
+    if ((int64_t)grid * sw > w.scratch_words) {
+        int rc = grow(&w.scratch, (int64_t)grid * sw);
+        if (rc) {
+            w.scratch_words = 0;
+            return rc;
+        }
+        w.scratch_words = (int64_t)grid * sw;
+        changed = true;
     }
-    w.scratch_words = need;
-    w.drop_graphs();
+    if (changed) w.drop_graphs();
+    v->pair_cell = w.pair_cell;
+    v->perm = w.perm;
+    v->cell_count = w.cell_count;
+    v->rank_start = w.rank_start;
+    v->counters = w.counters;
+    v->scratch = w.scratch;
+    v->slot_words = sw;
+    v->grid = grid;
+    v->base = w.scratch;
     return SW_OK;
 }
 
@@ -365,6 +440,8 @@ int ensure_scratch(Workspace& w, int64_t need)
 template <typename F>
 int capture(Device& d, F launch, hipGraphExec_t* out)
 {
+    if (!d.capture_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&d.capture_stream, hipStreamNonBlocking), "hipStreamCreate");
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(d.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t e1 = launch(d.capture_stream);
@@ -462,9 +539,16 @@ int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, size_t 
     return SW_OK;
 }
 
-int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
-                  const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
-                  const sw_scoring* scoring, sw_result* out_dev, void* stream_, uint32_t flags)
+}  // extern "C"
+
+namespace {
+
+// sw_align_sets with the device workspace either the library's (ws_dev
+// NULL) or the caller's buffer.
+int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+               const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+               const sw_scoring* scoring, sw_result* out_dev, void* ws_dev, size_t ws_bytes, void* stream_,
+               uint32_t flags)
 {
     if (!scoring || n_pairs < 0 || n_q < 0 || n_r < 0) return SW_EINVAL;
     if (flags & ~(SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH | SW_TIMED)) return SW_EINVAL;
@@ -476,6 +560,7 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
         return SW_EINVAL;
     if ((reinterpret_cast<uintptr_t>(q_packed_dev) | reinterpret_cast<uintptr_t>(r_packed_dev)) & 15u)
         return SW_EINVAL;
+    if (ws_dev && (reinterpret_cast<uintptr_t>(ws_dev) & (kWsAlign - 1))) return SW_EINVAL;
     if (n_pairs > (int64_t)0x7FFFFFFF - 64 || n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF)
         return SW_ERANGE;
     hipStream_t stream = (hipStream_t)stream_;
@@ -485,12 +570,15 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     int rc = get_device(&dp);
     if (rc) return rc;
     Device& d = *dp;
-    const int grid = d.n_cu * blocks_per_cu(d);
     Workspace* wp = nullptr;
-    if ((rc = get_workspace(d, stream, n_pairs, &wp))) return rc;
+    if ((rc = get_workspace(d, stream, &wp))) return rc;
     Workspace& w = *wp;
-    const int64_t sw_words = slot_words();
-    if ((rc = ensure_scratch(w, (int64_t)grid * sw_words))) return rc;
+    WsView v;
+    if (ws_dev) rc = carve_workspace(ws_dev, ws_bytes, n_pairs, d.n_cu * blocks_per_cu(d), &v);
+    else rc = library_workspace(w, n_pairs, d.n_cu * blocks_per_cu(d), &v);
+    if (rc) return rc;
+    const int grid = v.grid;
+    const int64_t sw_words = v.slot_words;
 
     Args a;
     std::memset(&a, 0, sizeof(a));
@@ -505,13 +593,13 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     a.pairs = pairs_dev;
     a.n_pairs = n_pairs;
     a.out = out_dev;
-    a.pair_cell = w.pair_cell;
-    a.perm = w.perm;
-    a.cell_count = w.cell_count;
-    a.rank_start = w.rank_start;
-    a.counters = w.counters;
+    a.pair_cell = v.pair_cell;
+    a.perm = v.perm;
+    a.cell_count = v.cell_count;
+    a.rank_start = v.rank_start;
+    a.counters = v.counters;
     a.err = d.err;
-    a.scratch = w.scratch;
+    a.scratch = v.scratch;
     a.slot_words = sw_words;
     a.go = scoring->gap_open;
     a.ge = scoring->gap_extend;
@@ -559,10 +647,12 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
     };
 
     if (flags & SW_PLAIN) {
+        if (!w.host_rank_start)
+            HIP_TRY(hipHostMalloc((void**)&w.host_rank_start, sizeof(int32_t) * (kNumCells + 1)), "hipHostMalloc");
         a.rank_cell = d.rank_cell_plain;
         a.phase = 0;
         HIP_TRY(launch_prepare(a, stream), "prepare launch");
-        HIP_TRY(hipMemcpyAsync(w.host_rank_start, w.rank_start, sizeof(int32_t) * (kNumCells + 1),
+        HIP_TRY(hipMemcpyAsync(w.host_rank_start, v.rank_start, sizeof(int32_t) * (kNumCells + 1),
                                hipMemcpyDeviceToHost, stream),
                 "bucket sizes");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
@@ -595,7 +685,8 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
             HIP_TRY(end_timed(1), "hipEventRecord");
         } else {
             GraphKey key{q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev,
-                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, d.group8_max, d.group16_max, grid, sw_words};
+                         n_pairs, a.go, a.ge, out_dev, d.R, d.inter_max, d.group8_max, d.group16_max, grid, sw_words,
+                         v.base};
             auto it = w.graphs.find(key);
             if (it == w.graphs.end()) {
                 if (w.graphs.size() >= 16) {
@@ -626,6 +717,43 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
         finish_timed();
     }
     if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                  const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+                  const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
+{
+    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
+                      out_dev, nullptr, 0, stream, flags);
+}
+
+int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                     const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+                     const sw_scoring* scoring, sw_result* out_dev, void* workspace_dev, size_t workspace_bytes,
+                     void* stream, uint32_t flags)
+{
+    if (!workspace_dev) return SW_EINVAL;
+    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
+                      out_dev, workspace_dev, workspace_bytes, stream, flags);
+}
+
+int sw_workspace_size(int64_t n_pairs, int64_t max_len, size_t* bytes)
+{
+    if (!bytes || n_pairs < 0 || max_len < 0) return SW_EINVAL;
+    *bytes = 0;
+    if (max_len > SW_MAX_SEQ_LEN) return SW_ERANGE;
+    if (n_pairs > (int64_t)0x7FFFFFFF - 64) return SW_ERANGE;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* d = nullptr;
+    int rc = get_device(&d);
+    if (rc) return rc;
+    const int64_t grid = (int64_t)d->n_cu * blocks_per_cu(*d);
+    *bytes = ws_head_bytes(n_pairs) + (size_t)grid * sizeof(uint32_t) * (size_t)slot_words_for(max_len);
     return SW_OK;
 }
 
@@ -660,7 +788,7 @@ int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     int rc = get_device(&dp);
     if (rc) return rc;
     Workspace* wp = nullptr;
-    if ((rc = get_workspace(*dp, stream, 0, &wp))) return rc;
+    if ((rc = get_workspace(*dp, stream, &wp))) return rc;
     if (!wp->discover) wp->discover.reset(new DiscoverSpace());
     DiscoverSpace& x = *wp->discover;
     if (!x.counters) {
@@ -813,7 +941,7 @@ int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     if (rc) return rc;
     Device& d = *dp;
     Workspace* wp = nullptr;
-    if ((rc = get_workspace(d, stream, 0, &wp))) return rc;
+    if ((rc = get_workspace(d, stream, &wp))) return rc;
     Workspace& w = *wp;
     if (!w.ident_subst) {
         // the substitution matrix re-indexed by packed code

@@ -1529,6 +1529,13 @@ __global__ void k_scatter(Args a)
 // ------------------------------------------------------------------ launchers
 size_t lds_bytes(int R) { return (size_t)kNumCodes * kWave * prof_bytes(R) + kXbufBytes; }
 
+int64_t slot_words_for(int64_t max_len)
+{
+    const int64_t n = std::min<int64_t>(std::max<int64_t>(max_len, 0), SW_MAX_SEQ_LEN);
+    const int64_t wide = n > kMaxP16Len ? 3 * wide_buf_words((int)n) : 0;
+    return std::max(slot_words(), (wide + 63) & ~(int64_t)63);
+}
+
 int64_t slot_words()
 {
     // [chunk][group][8 cells]: 64 groups of one lane over at most 128 chunks
@@ -1540,6 +1547,24 @@ int64_t slot_words()
     const int64_t p16 = 3 * boundary_buf_words(16);
     const int64_t p64 = kWideBufWords;  // whole wave, longest pairs: one buffer, in place
     return std::max(std::max(p1, p8), std::max(p16, p64));
+}
+
+// ------------------------------------------------------------------ per-device arrays
+// Tables every call reads (filled by the host at set-up) and the error word.
+static __device__ __align__(256) int32_t g_rank_cell[2][kNumCells];
+static __device__ __align__(256) int32_t g_err_word[64];
+
+hipError_t device_statics(DeviceStatics* s)
+{
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_rank_cell));
+    if (e != hipSuccess) return e;
+    s->rank_cell_persistent = static_cast<int32_t*>(p);
+    s->rank_cell_plain = static_cast<int32_t*>(p) + kNumCells;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_word));
+    if (e != hipSuccess) return e;
+    s->err = static_cast<int32_t*>(p);
+    return hipSuccess;
 }
 
 __global__ void k_pack_header(PackedHeader* h, int64_t n)

@@ -109,7 +109,23 @@ hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream);
 hipError_t launch_plain(const Args& a, int kind, int first, int count, int grid, hipStream_t stream);
 hipError_t set_kernel_attributes();
 size_t lds_bytes(int rows_per_lane);
+// 32-bit words of a block's boundary-row slot: slot_words() is the least that
+// serves every kind of work item (pairs too long for three whole-wave
+// buffers then sweep in place); slot_words_for(len) also gives every pair up
+// to len reference residues the whole-wave scan (three buffers).
 int64_t slot_words();
+int64_t slot_words_for(int64_t max_len);
+
+// Per-device state held in file-scope device arrays of sw_device.hip (no
+// allocation): the two rank -> cell orderings and the error word.
+// device_statics() looks their addresses up on the current device
+// (hipGetSymbolAddress); each device has its own copy of every array.
+struct DeviceStatics {
+    int32_t* rank_cell_persistent;
+    int32_t* rank_cell_plain;
+    int32_t* err;
+};
+hipError_t device_statics(DeviceStatics* out);
 void matrix_ncbi(int8_t out[kNumSym * kNumSym], char letters[kNumSym + 1]);
 const char* code_order();
 

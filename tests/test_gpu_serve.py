@@ -98,3 +98,64 @@ def test_admission_limits(setup):
         assert one.stats()["inflight"] == 0
     finally:
         one.close()
+
+
+def test_c5_shaped_set_under_admission_pressure():
+    """200,000 resident references (4,000 families x 50), query batches of
+    1 to 2,000 sequences with their k-mer candidate lists, all offered at
+    once to a server whose budget holds about one large request: requests
+    wait for admission (SW_EAGAIN) and memory, yet every request's results
+    equal the oracle's and its results when served alone."""
+    import os
+    import torch
+    import paper_2303_01845_amd as sw
+    from paper_2303_01845_amd.serve import Server, run_open_loop
+    sizes = [2000, 1200, 700, 300, 120, 50, 20, 8, 3, 1, 2000, 450]
+    say("generating the C5-shaped serving set (200k references)")
+    w = P.serving(n_fam=4000, per_fam=50, sizes=sizes, seed=2)
+    say("references %d, requests %d, candidates %d" % (len(w.ref_offsets) - 1, len(w.batches),
+                                                      sum(len(b[2]) for b in w.batches)))
+    refs = sw.Batch(w.ref_ascii, w.ref_offsets)
+    need = max(Server.request_bytes(len(q), len(qo) - 1, len(c)) for q, qo, c in w.batches)
+    srv = Server(refs.packed, refs.offsets, hbm_budget=need + need // 4, max_slots=4)
+
+    class Counting:
+        rejected = 0
+
+        def submit(self, *a):
+            t = srv.submit(*a)
+            if t is None:
+                Counting.rejected += 1
+            return t
+
+        def poll(self, t):
+            return srv.poll(t)
+
+    try:
+        alone = []
+        for q, qo, cand in w.batches:
+            t = srv.submit(q, qo, cand)
+            assert t is not None
+            alone.append(srv.wait(t))
+        say("alone done")
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        for k, (q, qo, cand) in enumerate(w.batches):
+            asc = np.concatenate([q, w.ref_ascii])
+            offs = np.concatenate([qo, w.ref_offsets[1:] + qo[-1]])
+            pairs = cand.copy()
+            pairs[:, 1] += len(qo) - 1
+            exp = oracle.batch_ascii(asc, offs, pairs, 11, 1, threads=threads)
+            assert (alone[k] == exp).all(), "request %d (%d queries) differs from the oracle" % (k, sizes[k])
+        say("oracle equal on every request")
+        rec = run_open_loop(Counting(), w.batches, np.zeros(len(w.batches)))
+        say("all offered at once: %d submits refused for budget" % Counting.rejected)
+        assert Counting.rejected > 0
+        for k, r in enumerate(rec):
+            assert (r["result"] == alone[k]).all(), "request %d differs in the mix" % k
+        rng = np.random.default_rng(3)
+        rec = run_open_loop(Counting(), w.batches, np.cumsum(rng.exponential(0.002, len(w.batches))))
+        for k, r in enumerate(rec):
+            assert (r["result"] == alone[k]).all(), "request %d differs under Poisson arrivals" % k
+        assert srv.stats()["bytes_in_use"] == 0
+    finally:
+        srv.close()

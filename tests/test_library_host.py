@@ -144,3 +144,28 @@ def test_identity_argument_checks_precede_device_use():
     assert _identity_raw(n_pairs=-1) == sw.SW_EINVAL
     assert _identity_raw(null=True) == sw.SW_EINVAL
     assert _identity_raw(n_pairs=1 << 31) == sw.SW_ERANGE
+
+
+def _ws_raw(ws=0x100000, ws_bytes=1 << 30, go=11, ge=1, n_pairs=3, flags=0, null=False):
+    L = sw.lib()
+    sc = sw.Scoring(0, go, ge)
+    p = ctypes.c_void_p(0 if null else 0x1000)
+    return L.sw_align_sets_ws(p, p, 10, p, p, 10, p, n_pairs, ctypes.byref(sc), p, ctypes.c_void_p(ws), ws_bytes,
+                              None, flags)
+
+
+def test_caller_workspace_argument_checks_precede_device_use():
+    assert _ws_raw(ws=0) == sw.SW_EINVAL                     # the workspace is required
+    assert _ws_raw(ws=0x100010) == sw.SW_EINVAL              # not 256-byte aligned
+    assert _ws_raw(go=0, ge=0) == sw.SW_EINVAL
+    assert _ws_raw(flags=64) == sw.SW_EINVAL
+    assert _ws_raw(null=True) == sw.SW_EINVAL
+    assert _ws_raw(n_pairs=-1) == sw.SW_EINVAL
+    assert _ws_raw(n_pairs=0) == sw.SW_OK                    # nothing to do
+    L = sw.lib()
+    b = ctypes.c_size_t(7)
+    assert L.sw_workspace_size(10, 100, None) == sw.SW_EINVAL
+    assert L.sw_workspace_size(-1, 100, ctypes.byref(b)) == sw.SW_EINVAL
+    assert L.sw_workspace_size(10, -1, ctypes.byref(b)) == sw.SW_EINVAL
+    assert L.sw_workspace_size(10, sw.MAX_SEQ_LEN + 1, ctypes.byref(b)) == sw.SW_ERANGE
+    assert b.value == 0

@@ -421,12 +421,12 @@ class ServeWorkload:
 
 
 def serving(n_fam: int = 20000, per_fam: int = 50, n_batches: int = 200, max_batch: int = 10000,
-            top: int = 200, seed: int = 0, workers: int | None = None) -> ServeWorkload:
+            top: int = 200, seed: int = 0, workers: int | None = None, sizes=None) -> ServeWorkload:
     """Reference set: n_fam families x per_fam members (ancestors LN(280, 0.6)
     clipped 30-5000, members Mutation(ancestor, U(0.2, 0.6), 0.03)).  Query
-    batches: sizes log-uniform on [1, max_batch]; each query a fresh member of
-    a random family; candidates: references sharing >= 2 distinct exact 6-mers,
-    the `top` most-shared first."""
+    batches: sizes log-uniform on [1, max_batch] (or the given ``sizes``);
+    each query a fresh member of a random family; candidates: references
+    sharing >= 2 distinct exact 6-mers, the `top` most-shared first."""
     rng = rng_for(5, seed)
     La = lognormal_lengths(rng, n_fam, 280.0, 0.6, 30, 5000)
     anc, anc_o = _from_lengths(rng, La)
@@ -435,7 +435,9 @@ def serving(n_fam: int = 20000, per_fam: int = 50, n_batches: int = 200, max_bat
     src_o = np.concatenate([[0], np.cumsum(La[fam])])
     ref, ref_o = mutate_many(rng, src, src_o, rng.uniform(0.2, 0.6, len(fam)), 0.03)
     index = KmerIndex(ref, ref_o)
-    sizes = np.exp(rng.uniform(0.0, np.log(max_batch + 1), n_batches)).astype(np.int64).clip(1, max_batch)
+    drawn = np.exp(rng.uniform(0.0, np.log(max_batch + 1), n_batches)).astype(np.int64).clip(1, max_batch)
+    sizes = drawn if sizes is None else np.asarray(sizes, dtype=np.int64)
+    n_batches = len(sizes)
     global _SERVE_STATE
     _SERVE_STATE = (anc, anc_o, La, n_fam, index, top)
     try:
