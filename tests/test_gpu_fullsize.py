@@ -3,13 +3,14 @@ times (persistent form, HIP graph, default tuning).
 
 * The 1M log-normal set and the 50k x 50k block set: every pair against the
   CPU oracle, bit for bit on all five outputs (the oracle runs on all host
-  threads, about a minute per set), and the plain form equal to the
-  persistent one on every pair.
+  threads, about a minute per set, checked in four slices so that no test
+  runs long without reporting), and the plain form equal to the persistent
+  one on every pair.
 * The heavy-tailed batching mix: its first seeded chunk (65,536 pairs, about
   3,300 of them 5,000-35,000 residues long) aligned in one call; every short
   pair against the oracle, plus 500 long pairs: the 20 costliest and 480
-  drawn at random.  The whole 10M-pair mix is 153 such chunks drawn the same
-  way, so this is one chunk-sized shard of it.
+  drawn at random, in five slices of 100.  The whole 10M-pair mix is 153 such
+  chunks drawn the same way, so this is one chunk-sized shard of it.
 """
 import os
 import sys
@@ -24,6 +25,7 @@ from workloads import proteins as P
 pytestmark = pytest.mark.gpu
 
 THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+SLICES = 4
 
 
 def say(msg):
@@ -82,7 +84,9 @@ def assert_rows(got, exp, idx, label):
             label, len(bad), len(got), pid, got[k].tolist(), exp[k].tolist()))
 
 
-def full_check(sw, ps, label):
+def aligned_set(sw, ps, label):
+    """Persistent results of every pair, checked for bounds and against the
+    plain form."""
     say("%s: %d pairs, %.4g cells, longest %d" % (label, ps.n_pairs, ps.cells(), ps.lengths().max()))
     got = align(sw, ps, sw.PERSISTENT)
     say("%s: aligned (persistent + graph)" % label)
@@ -91,21 +95,40 @@ def full_check(sw, ps, label):
     diff = np.flatnonzero((got != plain).any(axis=1))
     assert len(diff) == 0, "%s: persistent and plain differ on %d pairs (first %d)" % (label, len(diff), diff[0])
     say("%s: plain form equal on every pair" % label)
-    assert_rows(got, oracle_rows(ps, None), None, label)
-    say("%s: all %d pairs bit-exact against the oracle" % (label, ps.n_pairs))
+    return ps, got
 
 
-def test_lognormal_1m_every_pair(sw):
+def check_slice(state, k, label):
+    ps, got = state
+    idx = np.array_split(np.arange(ps.n_pairs), SLICES)[k]
+    assert_rows(got[idx], oracle_rows(ps, idx), idx, "%s slice %d" % (label, k))
+    say("%s: slice %d (%d pairs) bit-exact against the oracle" % (label, k, len(idx)))
+
+
+@pytest.fixture(scope="module")
+def lognormal(sw):
     say("generating the 1M log-normal workload")
-    full_check(sw, P.config_1m(1_000_000), "1M log-normal")
+    return aligned_set(sw, P.config_1m(1_000_000), "1M log-normal")
 
 
-def test_block_all_vs_all_every_pair(sw):
+@pytest.fixture(scope="module")
+def block(sw):
     say("generating the block all-vs-all workload (k-mer candidates)")
-    full_check(sw, P.config_block(), "block 50k x 50k")
+    return aligned_set(sw, P.config_block(), "block 50k x 50k")
 
 
-def test_heavy_tail_chunk_shard(sw):
+@pytest.mark.parametrize("k", range(SLICES))
+def test_lognormal_1m_every_pair(lognormal, k):
+    check_slice(lognormal, k, "1M log-normal")
+
+
+@pytest.mark.parametrize("k", range(SLICES))
+def test_block_all_vs_all_every_pair(block, k):
+    check_slice(block, k, "block 50k x 50k")
+
+
+@pytest.fixture(scope="module")
+def heavy(sw):
     say("generating chunk 0 of the heavy-tailed batching mix")
     ps = P.config_batching(P.CHUNK)
     L = ps.lengths().astype(np.int64)
@@ -116,17 +139,28 @@ def test_heavy_tail_chunk_shard(sw):
     got = align(sw, ps, sw.PERSISTENT)
     say("heavy tail shard: aligned")
     check_properties(ps, got)
-    short_idx = np.flatnonzero(~long_)
-    assert_rows(got[short_idx], oracle_rows(ps, short_idx), short_idx, "heavy tail short pairs")
-    say("heavy tail shard: all %d short pairs bit-exact" % len(short_idx))
     long_idx = np.flatnonzero(long_)
     cost = (m * n)[long_idx]
     top = long_idx[np.argsort(cost)[-20:]]
     rest = np.setdiff1d(long_idx, top)
     rng = np.random.default_rng(13)
-    pick = np.sort(np.concatenate([top, rng.choice(rest, 480, replace=False)]))
-    assert len(pick) == 500
+    pick = np.concatenate([top, rng.choice(rest, 480, replace=False)])
+    assert len(np.unique(pick)) == 500
     say("heavy tail shard: 500 long pairs (20 costliest up to %d x %d), %.4g cells" % (
         int(m[top[-1]]), int(n[top[-1]]), float((m * n)[pick].sum())))
-    assert_rows(got[pick], oracle_rows(ps, pick), pick, "heavy tail long pairs")
-    say("heavy tail shard: 500 long pairs bit-exact")
+    return ps, got, np.flatnonzero(~long_), pick
+
+
+def test_heavy_tail_short_pairs(heavy):
+    ps, got, short_idx, _ = heavy
+    assert_rows(got[short_idx], oracle_rows(ps, short_idx), short_idx, "heavy tail short pairs")
+    say("heavy tail shard: all %d short pairs bit-exact" % len(short_idx))
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_heavy_tail_long_pairs(heavy, k):
+    """Slice k of the 500 long pairs (slice 0 holds the 20 costliest)."""
+    ps, got, _, pick = heavy
+    idx = np.sort(pick[100 * k:100 * (k + 1)])
+    assert_rows(got[idx], oracle_rows(ps, idx), idx, "heavy tail long pairs, slice %d" % k)
+    say("heavy tail shard: long pairs %d..%d bit-exact" % (100 * k, 100 * k + 99))
