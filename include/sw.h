@@ -185,6 +185,28 @@ SW_API int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_d
                             uint32_t flags);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP-graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sw_align_sets
+ * with its device workspace in a fixed array that the library holds on every
+ * device it is loaded on (256 MiB, kept until the process ends).  The call
+ * allocates nothing, host or device: it runs the persistent form without HIP
+ * graphs and a smaller grid than sw_align_sets (as many blocks as boundary-row
+ * slots fit the array), with the same results.  Every call on a device shares
+ * that device's array and leaves its contents behind (each call clears what
+ * it needs): calls that overlap in time on one device -- on two streams, or
+ * from two host threads -- race and must not be issued.
+ * flags: SW_VALIDATE, SW_NO_GRAPH (implied); SW_PLAIN and SW_TIMED are refused
+ * (SW_EINVAL: both need host state the library would allocate).
+ * Errors: as sw_align_sets, plus SW_ENOMEM (with a message in
+ * sw_last_device_error) for more than 4,194,304 pairs, the most the array
+ * holds.
+ */
+SW_API int sw_align_sets_static(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                                const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
+                                const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring,
+                                sw_result* out_dev, void* stream, uint32_t flags);
+
+/*
  * Error check of the driver (section "Software stack and parallelism"): the
  * kernels record invalid input in a device word instead of stopping.
  * Synchronise `stream`, then return and clear the device-detected errors

@@ -34,6 +34,7 @@ COVERAGE_FIRST = 16
 
 # every function the C header declares
 EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_align_sets_ws",
+           "sw_align_sets_static",
            "sw_workspace_size", "sw_check", "sw_timing_read",
            "sw_timing_read_passes", "sw_set_tuning",
            "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
@@ -93,6 +94,10 @@ def lib():
                                        ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                        ctypes.c_uint32]
+        L.sw_align_sets_static.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Scoring),
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
         L.sw_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
         L.sw_check.argtypes = [ctypes.c_void_p]
         L.sw_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -233,6 +238,27 @@ def align_sets_ws(q_packed, q_offsets, r_packed, r_offsets, pairs, workspace, ga
                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
                                   int(workspace.numel() * workspace.element_size()), _stream_ptr(stream),
                                   int(flags)), "sw_align_sets_ws")
+    return out
+
+
+def align_sets_static(q_packed, q_offsets, r_packed, r_offsets, pairs, gap_open: int = 11,
+                      gap_extend: int = 1, flags: int = PERSISTENT, out=None, stream=None):
+    """align_sets through the entry point that allocates nothing (its
+    workspace is the library's fixed per-device array).  ``out`` must be
+    given by callers that cannot allocate."""
+    import torch
+    n_pairs = int(pairs.shape[0]) if pairs.dim() == 2 else int(pairs.numel() // 2)
+    if out is None:
+        out = torch.empty((n_pairs, 5), dtype=torch.int32, device=pairs.device)
+    assert q_offsets.dtype == torch.int64 and r_offsets.dtype == torch.int64
+    assert pairs.dtype == torch.int32 and out.dtype == torch.int32 and pairs.is_contiguous()
+    sc = Scoring(0, int(gap_open), int(gap_extend))
+    _check(lib().sw_align_sets_static(ctypes.c_void_p(q_packed.data_ptr()), ctypes.c_void_p(q_offsets.data_ptr()),
+                                      int(q_offsets.numel()) - 1, ctypes.c_void_p(r_packed.data_ptr()),
+                                      ctypes.c_void_p(r_offsets.data_ptr()), int(r_offsets.numel()) - 1,
+                                      ctypes.c_void_p(pairs.data_ptr()), n_pairs, ctypes.byref(sc),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), int(flags)),
+           "sw_align_sets_static")
     return out
 
 

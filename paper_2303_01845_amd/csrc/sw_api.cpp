@@ -256,6 +256,7 @@ struct Device {
     int32_t* rank_cell_persistent = nullptr;  // file-scope device arrays (device_statics)
     int32_t* rank_cell_plain = nullptr;
     int32_t* err = nullptr;
+    void* static_ws = nullptr;                // kStaticWsBytes (sw_align_sets_static)
     hipStream_t capture_stream = nullptr;     // created by the first graph capture
     std::map<hipStream_t, std::unique_ptr<Workspace>> ws;
 };
@@ -296,6 +297,7 @@ int get_device(Device** out)
         d.rank_cell_persistent = st.rank_cell_persistent;
         d.rank_cell_plain = st.rank_cell_plain;
         d.err = st.err;
+        d.static_ws = st.static_ws;
         HIP_TRY(hipMemset(d.err, 0, sizeof(int32_t)), "hipMemset");
         int rc = upload_ordering(d);
         if (rc != SW_OK) return rc;
@@ -543,44 +545,11 @@ int sw_pack(const char* ascii_dev, int64_t n_residues, void* packed_dev, size_t 
 
 namespace {
 
-// sw_align_sets with the device workspace either the library's (ws_dev
-// NULL) or the caller's buffer.
-int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
-               const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
-               const sw_scoring* scoring, sw_result* out_dev, void* ws_dev, size_t ws_bytes, void* stream_,
-               uint32_t flags)
+// Kernel arguments of one alignment call (phase and ordering set by the caller).
+void fill_args(Args& a, const Device& d, const WsView& v, const void* q_packed_dev, const int64_t* q_offsets_dev,
+               int64_t n_q, const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r,
+               const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev)
 {
-    if (!scoring || n_pairs < 0 || n_q < 0 || n_r < 0) return SW_EINVAL;
-    if (flags & ~(SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH | SW_TIMED)) return SW_EINVAL;
-    if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
-        scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
-        return SW_EINVAL;
-    if (n_pairs == 0) return SW_OK;
-    if (!q_packed_dev || !q_offsets_dev || !r_packed_dev || !r_offsets_dev || !pairs_dev || !out_dev)
-        return SW_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(q_packed_dev) | reinterpret_cast<uintptr_t>(r_packed_dev)) & 15u)
-        return SW_EINVAL;
-    if (ws_dev && (reinterpret_cast<uintptr_t>(ws_dev) & (kWsAlign - 1))) return SW_EINVAL;
-    if (n_pairs > (int64_t)0x7FFFFFFF - 64 || n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF)
-        return SW_ERANGE;
-    hipStream_t stream = (hipStream_t)stream_;
-
-    std::lock_guard<std::mutex> lock(g_mutex);
-    Device* dp = nullptr;
-    int rc = get_device(&dp);
-    if (rc) return rc;
-    Device& d = *dp;
-    Workspace* wp = nullptr;
-    if ((rc = get_workspace(d, stream, &wp))) return rc;
-    Workspace& w = *wp;
-    WsView v;
-    if (ws_dev) rc = carve_workspace(ws_dev, ws_bytes, n_pairs, d.n_cu * blocks_per_cu(d), &v);
-    else rc = library_workspace(w, n_pairs, d.n_cu * blocks_per_cu(d), &v);
-    if (rc) return rc;
-    const int grid = v.grid;
-    const int64_t sw_words = v.slot_words;
-
-    Args a;
     std::memset(&a, 0, sizeof(a));
     a.qblk = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(q_packed_dev) + kHeaderBytes);
     a.qhdr = reinterpret_cast<const PackedHeader*>(q_packed_dev);
@@ -600,13 +569,91 @@ int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n
     a.counters = v.counters;
     a.err = d.err;
     a.scratch = v.scratch;
-    a.slot_words = sw_words;
+    a.slot_words = v.slot_words;
     a.go = scoring->gap_open;
     a.ge = scoring->gap_extend;
     a.rows_per_lane = d.R;
     a.inter_max_len = d.inter_max;
     a.group16_max_len = d.group16_max;
     a.group8_max_len = d.group8_max;
+}
+
+// Where the device arrays of a call come from.
+enum class WsMode {
+    library,  // the library's per-stream arrays, grown on demand
+    caller,   // one buffer the caller owns
+    fixed,    // the file-scope device array of this device: nothing is allocated
+};
+
+// sw_align_sets with the device workspace chosen by `mode` (ws_dev and
+// ws_bytes describe the caller's buffer).  In the fixed mode the call touches
+// neither the per-stream state nor any allocator: persistent form without
+// graphs, no timing events, no pinned buffer.
+int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+               const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+               const sw_scoring* scoring, sw_result* out_dev, WsMode mode, void* ws_dev, size_t ws_bytes,
+               void* stream_, uint32_t flags)
+{
+    if (!scoring || n_pairs < 0 || n_q < 0 || n_r < 0) return SW_EINVAL;
+    if (flags & ~(SW_PLAIN | SW_VALIDATE | SW_NO_GRAPH | SW_TIMED)) return SW_EINVAL;
+    if (mode == WsMode::fixed) {
+        if (flags & (SW_PLAIN | SW_TIMED)) return SW_EINVAL;
+        flags |= SW_NO_GRAPH;
+    }
+    if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
+        scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
+        return SW_EINVAL;
+    if (n_pairs == 0) return SW_OK;
+    if (!q_packed_dev || !q_offsets_dev || !r_packed_dev || !r_offsets_dev || !pairs_dev || !out_dev)
+        return SW_EINVAL;
+    if (mode == WsMode::fixed && n_pairs > kStaticMaxPairs) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "sw_align_sets_static: %lld pairs, at most %lld fit its fixed workspace", (long long)n_pairs,
+                      (long long)kStaticMaxPairs);
+        return SW_ENOMEM;
+    }
+    if ((reinterpret_cast<uintptr_t>(q_packed_dev) | reinterpret_cast<uintptr_t>(r_packed_dev)) & 15u)
+        return SW_EINVAL;
+    if (ws_dev && (reinterpret_cast<uintptr_t>(ws_dev) & (kWsAlign - 1))) return SW_EINVAL;
+    if (n_pairs > (int64_t)0x7FFFFFFF - 64 || n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF)
+        return SW_ERANGE;
+    hipStream_t stream = (hipStream_t)stream_;
+
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* dp = nullptr;
+    int rc = get_device(&dp);
+    if (rc) return rc;
+    Device& d = *dp;
+    WsView v;
+    if (mode == WsMode::fixed) {
+        rc = carve_workspace(d.static_ws, kStaticWsBytes, n_pairs, d.n_cu * blocks_per_cu(d), &v);
+        if (rc) return rc;
+        Args a;
+        fill_args(a, d, v, q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs,
+                  scoring, out_dev);
+        a.rank_cell = d.rank_cell_persistent;
+        Args a1 = a, a2 = a;
+        a1.phase = 1;
+        a2.phase = 2;
+        HIP_TRY(launch_prepare(a1, stream), "prepare launch");
+        HIP_TRY(launch_persistent(a1, v.grid, stream), "persistent launch");
+        HIP_TRY(launch_prepare(a2, stream), "prepare launch");
+        HIP_TRY(launch_persistent(a2, v.grid, stream), "persistent launch");
+        if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
+        return SW_OK;
+    }
+    Workspace* wp = nullptr;
+    if ((rc = get_workspace(d, stream, &wp))) return rc;
+    Workspace& w = *wp;
+    if (mode == WsMode::caller) rc = carve_workspace(ws_dev, ws_bytes, n_pairs, d.n_cu * blocks_per_cu(d), &v);
+    else rc = library_workspace(w, n_pairs, d.n_cu * blocks_per_cu(d), &v);
+    if (rc) return rc;
+    const int grid = v.grid;
+    const int64_t sw_words = v.slot_words;
+
+    Args a;
+    fill_args(a, d, v, q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs,
+              scoring, out_dev);
 
     const bool timed = flags & SW_TIMED;
     std::pair<hipEvent_t, hipEvent_t> ev[2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -729,7 +776,15 @@ int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_
                   const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
 {
     return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
-                      out_dev, nullptr, 0, stream, flags);
+                      out_dev, WsMode::library, nullptr, 0, stream, flags);
+}
+
+int sw_align_sets_static(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                         const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev,
+                         int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
+{
+    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
+                      out_dev, WsMode::fixed, nullptr, 0, stream, flags);
 }
 
 int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
@@ -739,7 +794,7 @@ int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_dev, int
 {
     if (!workspace_dev) return SW_EINVAL;
     return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
-                      out_dev, workspace_dev, workspace_bytes, stream, flags);
+                      out_dev, WsMode::caller, workspace_dev, workspace_bytes, stream, flags);
 }
 
 int sw_workspace_size(int64_t n_pairs, int64_t max_len, size_t* bytes)

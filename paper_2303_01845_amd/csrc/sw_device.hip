@@ -1553,6 +1553,11 @@ int64_t slot_words()
 // Tables every call reads (filled by the host at set-up) and the error word.
 static __device__ __align__(256) int32_t g_rank_cell[2][kNumCells];
 static __device__ __align__(256) int32_t g_err_word[64];
+// Workspace of sw_align_sets_static (sort tables, pair arrays and boundary-row
+// slots, carved as a caller's buffer would be), for callers that cannot
+// allocate device memory.  Every device the library is loaded on holds its
+// own copy until the process ends; every call on a device shares it.
+static __device__ __align__(256) uint8_t scratch[kStaticWsBytes];
 
 hipError_t device_statics(DeviceStatics* s)
 {
@@ -1564,6 +1569,11 @@ hipError_t device_statics(DeviceStatics* s)
     e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_word));
     if (e != hipSuccess) return e;
     s->err = static_cast<int32_t*>(p);
+    // host code uses this address, never the array's own name (a host-side
+    // stand-in that is not a device address)
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    s->static_ws = p;
     return hipSuccess;
 }
 
