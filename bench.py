@@ -57,16 +57,24 @@ def main():
     ap.add_argument("--group8-max", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner on the workload before timing")
+    ap.add_argument("--autotune-cache", default=None, metavar="JSON",
+                    help="the autotuner's cache of per-bucket choices (read and rewritten)")
     ap.add_argument("--no-graph", action="store_true",
                     help="persistent form launched directly instead of replayed as a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration) and exit")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: open-loop request arrivals, p50/p99 latency")
-    ap.add_argument("--serve-families", type=int, default=4000)
-    ap.add_argument("--serve-batches", type=int, default=300)
-    ap.add_argument("--serve-max-batch", type=int, default=2000)
+    ap.add_argument("--serve-families", type=int, default=20000,
+                    help="reference families of 50 members (20000: the 1M-reference serving set)")
+    ap.add_argument("--serve-batches", type=int, default=200)
+    ap.add_argument("--serve-max-batch", type=int, default=10000)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--c3-shards", type=int, default=8,
+                    help="devices the 10M-pair heavy-tailed set is split over; one shard is timed")
+    ap.add_argument("--parts", default="c2,c3,serve",
+                    help="what the default run measures: c2 (the headline), c3 (a heavy-tail shard), "
+                         "serve (serving latency); c3 or serve alone only print that object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -84,9 +92,19 @@ def main():
         calibrate_copy(torch, dev, args.calibrate_copy)
         return
     if args.serve:
-        serve_bench(args)
+        res = serve_bench(args, (0.3, 0.6, 0.9))
+        print(json.dumps(res), flush=True)
         return
+    parts = set(args.parts.split(","))
     sw.lib()
+    if "c2" not in parts:
+        res = {}
+        if "c3" in parts:
+            res["c3_shard"] = c3_shard_bench(sw, torch, args)
+        if "serve" in parts:
+            res["serve"] = serve_bench(args, (0.3, 0.6, 0.9))
+        print(json.dumps(res), flush=True)
+        return
     if args.rows_per_lane or args.inter_max or args.blocks_per_cu or args.group16_max or args.group8_max:
         sw.set_tuning(args.rows_per_lane, args.inter_max, args.blocks_per_cu, args.group16_max, args.group8_max)
     tuning = sw.get_tuning()
@@ -127,8 +145,9 @@ def main():
                        packed_d.numel(), ctypes.c_void_p(sptr))
         if rc:
             raise sw.SwError(rc, "sw_pack")
-        chosen, ms = sw.autotune(packed_d, offs_d, pairs_d, 11, 1, reps=2, out=out_d, stream=stream)
-        log("autotune chose %s (%.2f ms per call)" % (chosen, ms))
+        chosen, ms, trials = sw.autotune(packed_d, offs_d, pairs_d, 11, 1, reps=2, out=out_d, stream=stream,
+                                         cache_path=args.autotune_cache)
+        log("autotune chose %s (%.2f ms per call, %d bucket trials)" % (chosen, ms, trials))
         tuning = sw.get_tuning()
 
     def timed(flags, steps, warmup, label):
@@ -238,15 +257,119 @@ def main():
     if args.workload == "block-50kx50k":
         res["identity"] = identity_bench(sw, torch, ps, packed_d, offs_d, pairs_d, out_d, stream, args)
         res["discovery"] = discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args)
-        # the whole search on one GPU: discover candidates, align them, filter
-        # by identity and coverage (cells are the alignment's m x n)
-        total_ms = res["discovery"]["ms"] + ms_per_step + res["identity"]["ms"]
-        res["pipeline"] = {"ms": round(total_ms, 3), "gcups": round(cells / (total_ms * 1e-3) / 1e9, 2),
-                           "stages": "sw_discover + sw_pack/sw_batch_align + sw_identity",
-                           "edges_kept": res["identity"]["kept"]}
+        res["pipeline"] = search_bench(sw, torch, ps, packed_d, offs_d, stream, args, res, ms_per_step, cells)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
+    if args.workload == "1m-lognormal280":
+        # free the headline workload before the larger ones
+        del ascii_d, offs_d, pairs_d, packed_d, out_d, ps
+        torch.cuda.empty_cache()
+        if "c3" in parts:
+            res["c3_shard"] = c3_shard_bench(sw, torch, args)
+        if "serve" in parts:
+            res["serve"] = serve_bench(args, (0.3, 0.6, 0.9))
     print(json.dumps(res), flush=True)
+
+
+def c3_shard_bench(sw, torch, args):
+    """One GPU's share of the 10M-pair heavy-tailed batching set: its chunks
+    (65,536 pairs each) assigned longest-first to --c3-shards devices by their
+    cost, the first shard generated, packed and aligned in one persistent
+    call (one untimed call first), timed by HIP events; results of a sample
+    of short and long pairs checked against the oracle.  The projected time
+    of the whole set on that many devices is the largest shard's cost at
+    this shard's rate."""
+    import ctypes
+    import oracle
+    from workloads import proteins as P
+    G = args.c3_shards
+    t0 = time.time()
+    shards, load, cost = P.c3_lpt_shards(G)
+    ps = P.c3_shard(shards[0])
+    cells = ps.cells()
+    L = ps.lengths().astype(np.int64)
+    m, n = L[ps.pairs[:, 0]], L[ps.pairs[:, 1]]
+    long_ = np.maximum(m, n) > 4096
+    log("c3 shard: %d of %d chunks, %d pairs (%d over 4096 residues), %.4g cells, generated in %.1fs" % (
+        len(shards[0]), len(cost), ps.n_pairs, int(long_.sum()), cells, time.time() - t0))
+    dev = torch.device("cuda:0")
+    ascii_d = torch.from_numpy(ps.ascii).to(dev)
+    offs_d = torch.from_numpy(ps.offsets).to(dev)
+    pairs_d = torch.from_numpy(ps.pairs).to(dev)
+    packed_d = torch.empty(sw.packed_bytes(ascii_d.numel()), dtype=torch.uint8, device=dev)
+    out_d = torch.empty((ps.n_pairs, 5), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+    Lb = sw.lib()
+    sc = sw.Scoring(0, 11, 1)
+    rc = Lb.sw_pack(ctypes.c_void_p(ascii_d.data_ptr()), ascii_d.numel(), ctypes.c_void_p(packed_d.data_ptr()),
+                    packed_d.numel(), sptr)
+    if rc:
+        raise sw.SwError(rc, "sw_pack")
+    del ascii_d
+
+    def call(flags):
+        rc = Lb.sw_batch_align(ctypes.c_void_p(packed_d.data_ptr()), ctypes.c_void_p(offs_d.data_ptr()), ps.n_seqs,
+                               ctypes.c_void_p(pairs_d.data_ptr()), ps.n_pairs, ctypes.byref(sc),
+                               ctypes.c_void_p(out_d.data_ptr()), sptr, flags)
+        if rc:
+            raise sw.SwError(rc, "sw_batch_align")
+
+    log("c3 shard: untimed call")
+    call(sw.PERSISTENT)
+    torch.cuda.synchronize()
+    sw.timing_read(stream)
+    log("c3 shard: timed call")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = time.perf_counter()
+    e0.record(stream)
+    call(sw.PERSISTENT | sw.TIMED)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    call_ms = e0.elapsed_time(e1)
+    fwd_ms, start_ms, _ = sw.timing_read_passes(stream)
+    got = out_d.cpu().numpy()
+    # oracle sample: 400 short pairs, the 2 costliest long pairs and 6 more
+    rng = np.random.default_rng(17)
+    short_idx = np.flatnonzero(~long_)
+    long_idx = np.flatnonzero(long_)
+    top = long_idx[np.argsort((m * n)[long_idx])[-2:]]
+    rest = np.setdiff1d(long_idx, top)
+    pick = np.sort(np.concatenate([rng.choice(short_idx, min(400, len(short_idx)), replace=False), top,
+                                   rng.choice(rest, min(6, len(rest)), replace=False)]))
+    sub = ps.subset(pick)
+    tc = time.perf_counter()
+    exp = oracle.batch_ascii(sub.ascii, sub.offsets, sub.pairs, 11, 1, threads=len(os.sched_getaffinity(0)))
+    n_ok = int((got[pick] == exp).all(axis=1).sum())
+    log("c3 shard: %.1f ms per call (forward %.1f, start %.1f), %.1f GCUPS; oracle sample %d/%d in %.1fs" % (
+        call_ms, fwd_ms, start_ms, cells / (call_ms * 1e-3) / 1e9, n_ok, len(pick), time.perf_counter() - tc))
+    kernel_ms = fwd_ms + start_ms
+    achieved = ALGO_OPS_PER_CELL * cells / (kernel_ms * 1e-3) / 1e12
+    wide = float((m * n)[long_].sum()) / cells
+    out = {
+        "workload": "heavy-tail 10M pairs, LPT shard 1 of %d (chunks of 65,536 pairs assigned longest-first "
+                    "by sum of squared query lengths)" % G,
+        "chunks": shards[0], "pairs": ps.n_pairs, "long_pairs": int(long_.sum()), "cells": cells,
+        "cells_share_over_4096": round(wide, 4),
+        "ms": round(call_ms, 2), "wall_ms": round(wall * 1e3, 2),
+        "gcups": round(cells / (call_ms * 1e-3) / 1e9, 2),
+        "alignments_per_s": round(ps.n_pairs / (call_ms * 1e-3), 1),
+        "forward_kernel_ms": round(fwd_ms, 2), "start_kernel_ms": round(start_ms, 2),
+        "gcups_fwd": round(cells / (fwd_ms * 1e-3) / 1e9, 2),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
+                     "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
+                     "peak_basis": "int32 VALU: %.1f%% of the cells are in pairs over 4,096 residues, "
+                                   "aligned by the int32 whole-wave path" % (100 * wide)},
+        "projected_full_set_s": round(call_ms * 1e-3 * float(load.max()) / float(load[0]), 2),
+        "projected_note": "the whole 10M-pair set on %d GPUs: the largest shard's cost at this shard's rate "
+                          "(no transfer or collective time)" % G,
+        "parity_sample": "%d/%d bit-exact vs CPU oracle (400 short, the 2 costliest and 6 more long pairs)" % (
+            n_ok, len(pick)),
+    }
+    del packed_d, offs_d, pairs_d, out_d
+    torch.cuda.empty_cache()
+    return out
 
 
 def identity_bench(sw, torch, ps, packed_d, offs_d, pairs_d, out_d, stream, args):
@@ -309,6 +432,39 @@ def identity_bench(sw, torch, ps, packed_d, offs_d, pairs_d, out_d, stream, args
                            "sample": "%d random pairs, %d box cells, %.2f s" % (len(sample), sample_cells, cpu_s)}}
 
 
+def search_bench(sw, torch, ps, packed_d, offs_d, stream, args, res, align_ms, cells):
+    """The whole search on the device (sw_search): discovery of the block
+    workload's candidates, their alignment and the identity / coverage filter,
+    in four query blocks with the next block's discovery overlapping the
+    current block's alignment.  Wall time per call (the call is synchronous),
+    beside the sum of the three stages timed alone; its edges are checked
+    against the stage calls' kept pairs."""
+    nq = (ps.n_seqs + 1) // 2
+    qo, ro = offs_d[:nq + 1], offs_d[nq:]
+    kept = res["identity"]["kept"]
+    cap = kept + 1024
+    out = None
+    for _ in range(2):
+        out = sw.search(packed_d, qo, packed_d, ro, block_queries=(nq + 3) // 4, edge_cap=cap, stream=stream)
+    steps = max(3, args.steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        out = sw.search(packed_d, qo, packed_d, ro, block_queries=(nq + 3) // 4, edge_cap=cap, stream=stream)
+    wall = (time.perf_counter() - t) / steps
+    st = out[3]
+    stage_ms = res["discovery"]["ms"] + align_ms + res["identity"]["ms"]
+    log("search: %.3f ms per call (%d blocks, %d candidates, %d edges); stages alone %.3f ms" % (
+        wall * 1e3, st["blocks"], st["candidates"], st["edges"], stage_ms))
+    return {"ms": round(wall * 1e3, 3), "gcups": round(cells / wall / 1e9, 2), "blocks": st["blocks"],
+            "candidates": st["candidates"], "edges": st["edges"], "edges_count_equals_stage_calls": st["edges"] == kept,
+            "stages_sum_ms": round(stage_ms, 3),
+            "stages": "sw_search: sw_discover per query block on one stream, sw_align_sets + sw_identity + edge "
+                      "compaction on another; stages_sum_ms adds the three stages timed alone (the alignment "
+                      "including packing)",
+            "steps": steps}
+
+
 def discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args):
     """Candidate discovery (sw_discover, k = 6, >= 2 shared) of the block
     workload's 50k queries against its 50k references, on the resident packed
@@ -360,7 +516,7 @@ def discovery_bench(sw, torch, ps, packed_d, offs_d, stream, args):
                            "candidates": int(len(oq))}}
 
 
-def serve_bench(args):
+def serve_bench(args, rhos):
     """Serving: a reference set resident in HBM (families x 50 members), query
     batches of log-uniform size with their k-mer candidates (top 200 per
     query), Poisson arrivals at offered loads 0.3 / 0.6 / 0.9 of the measured
@@ -392,7 +548,7 @@ def serve_bench(args):
         log("closed loop: %.1f ms for %d requests, %.1f GCUPS" % (span0 * 1e3, n, cap / 1e9))
         loads = {}
         rng = np.random.default_rng(11)
-        for rho in (0.3, 0.6, 0.9):
+        for rho in rhos:
             lam = rho * cap / cells.mean()
             arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
             arrivals -= arrivals[0]
@@ -418,24 +574,26 @@ def serve_bench(args):
             checked += len(cand)
     finally:
         srv.close()
+    last = str(rhos[-1])
     res = {
-        "metric": "serve latency p99 at offered load 0.9 (completion - arrival, host buffers)",
-        "value": loads["0.9"]["p99_ms"],
+        "metric": "serve latency p99 at offered load %s (completion - arrival, host buffers)" % last,
+        "value": loads[last]["p99_ms"],
         "unit": "ms",
         "n_gpus": 1,
         "higher_is_better": False,
         "data": "synthetic",
         "dtype": "u16x2+i32",
-        "config": {"workload": "serve-families%dx50" % args.serve_families, "requests": n,
+        "config": {"workload": "serve %d references (%d families x 50)" % (len(Lr), args.serve_families),
+                   "requests": n,
                    "max_batch": args.serve_max_batch, "slots": args.serve_slots, "hbm_budget_gib": 16,
                    "candidates": "refs sharing >= 2 distinct 6-mers, top 200 per query",
                    "mean_cells_per_request": float(cells.mean())},
         "capacity_gcups": round(cap / 1e9, 2),
         "loads": loads,
-        "parity": "every request identical across the closed loop and three open loops; "
+        "parity": "every request identical across the closed loop and the open loops; "
                   "%d candidates of the 4 smallest requests bit-exact vs CPU oracle" % checked,
     }
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def calibrate_copy(torch, dev, nbytes):

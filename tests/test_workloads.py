@@ -84,3 +84,15 @@ def test_shared_kmer_candidates():
         for j in range(len(r)):
             k = len(kmers(qa, qo, i) & kmers(ra, ro, j))
             assert ((i, j) in got) == (k >= 2)
+
+
+def test_c3_lpt_shard_is_the_seeded_chunks():
+    """The query lengths the LPT assignment replays are those of the chunks
+    config_batching draws, and the shards split the chunks exactly once."""
+    L = P._c3_query_lengths((5, 300, 0.05))
+    b = P.config_batching(300, first_chunk=5, workers=1)
+    assert (b.lengths()[b.pairs[:, 0]] == L).all()
+    shards, load, cost = P.c3_lpt_shards(3, n_pairs=5 * P.CHUNK + 1000, workers=1)
+    assert sorted(c for s in shards for c in s) == list(range(6))
+    assert abs(load.sum() - cost.sum()) < 1e-6 * cost.sum()
+    assert load.max() - load.min() <= cost.max()

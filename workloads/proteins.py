@@ -288,6 +288,55 @@ def config_batching(n_pairs: int, first_chunk: int = 0, long_frac: float = 0.05,
     return ps
 
 
+C3_PAIRS = 10_000_000  # the whole heavy-tailed batching set
+
+
+def _c3_chunk_sizes(n_pairs: int = C3_PAIRS):
+    """Pairs per chunk of the first n_pairs of the heavy-tailed set."""
+    full, rest = divmod(n_pairs, CHUNK)
+    return [CHUNK] * full + ([rest] if rest else [])
+
+
+def _c3_query_lengths(args):
+    """Query lengths of one heavy-tail chunk: the first draws of
+    _homolog_chunk replayed from the chunk's seed (no residues drawn)."""
+    c, k, long_frac = args
+    rng = rng_for(3, c)
+    Lq = lognormal_lengths(rng, k, 250.0, 0.6, 30, 5000)
+    if long_frac > 0:
+        is_long = rng.random(k) < long_frac
+        Lq[is_long] = rng.integers(5000, 35000 + 1, int(is_long.sum()))
+    return Lq
+
+
+def c3_lpt_shards(n_shards: int, n_pairs: int = C3_PAIRS, long_frac: float = 0.05, workers: int | None = None):
+    """Longest-processing-time assignment of the heavy-tailed set's chunks to
+    n_shards devices: chunks in decreasing order of cost (the sum of squared
+    query lengths, replayed from each chunk's seed; a pair costs about m * n
+    and the reference length is the query's within a few percent of indels),
+    each to the device with the least cost so far.  Returns (chunk lists per
+    shard, cost per shard, cost per chunk)."""
+    sizes = _c3_chunk_sizes(n_pairs)
+    Ls = _map_chunks(_c3_query_lengths, [(c, k, long_frac) for c, k in enumerate(sizes)], workers)
+    cost = np.array([float((L.astype(np.float64) ** 2).sum()) for L in Ls])
+    shards = [[] for _ in range(n_shards)]
+    load = np.zeros(n_shards)
+    for c in np.argsort(-cost, kind="stable"):
+        g = int(np.argmin(load))
+        shards[g].append(int(c))
+        load[g] += cost[c]
+    return [sorted(x) for x in shards], load, cost
+
+
+def c3_shard(chunks, n_pairs: int = C3_PAIRS, long_frac: float = 0.05, workers: int | None = None) -> PairSet:
+    """The pairs of the given chunks of the heavy-tailed set (each chunk drawn
+    from its own seed at its own size, exactly as config_batching draws it)."""
+    sizes = _c3_chunk_sizes(n_pairs)
+    ps = concat(_map_chunks(_c3_chunk, [(c, sizes[c], long_frac) for c in chunks], workers))
+    ps.name = "heavy-tail-shard-%dchunks" % len(chunks)
+    return ps
+
+
 def families(config: int, n_fam: int, n_members: int, d_lo: float = 0.20, d_hi: float = 0.60):
     """Family model: ancestors LN(280, 0.6) clipped 30-5000; each member picks a
     uniform family and is Mutation(ancestor, d ~ U(d_lo, d_hi), 0.03)."""
@@ -383,12 +432,16 @@ def config_block(n_fam: int = 2000, n_members: int = 100_000) -> PairSet:
 # --------------------------------------------------------------------------
 
 class KmerIndex:
-    """Sorted (k-mer, reference) list of the distinct exact k-mers of a set."""
+    """Distinct exact k-mers of a reference set, as blocks of sorted keys
+    k-mer * n + reference (one block per slice of references, built in
+    parallel; each block sorted by k-mer, then reference)."""
 
-    def __init__(self, asc, offs, k: int = 6):
-        km, seq = kmer_sets(asc, offs, k)
-        o = np.argsort(km, kind="stable")
-        self.km, self.seq, self.k, self.n = km[o], seq[o], k, len(offs) - 1
+    def __init__(self, asc, offs, k: int = 6, blocks=None):
+        self.k, self.n = k, len(offs) - 1
+        if blocks is None:
+            km, seq = kmer_sets(asc, offs, k)
+            blocks = [np.sort(km * self.n + seq)]
+        self.blocks = blocks
 
     def candidates(self, q_asc, q_offs, min_shared: int = 2, top: int = 200):
         """(query, reference, shared) with >= min_shared distinct shared k-mers,
@@ -396,12 +449,15 @@ class KmerIndex:
         qk, qs = kmer_sets(q_asc, q_offs, self.k)
         o = np.argsort(qk)  # sorted needles: numpy's binary search reuses the last bound
         qk, qs = qk[o], qs[o]
-        lo = np.searchsorted(self.km, qk, side="left")
-        hi = np.searchsorted(self.km, qk, side="right")
-        cnt = hi - lo
-        qrep = np.repeat(qs, cnt)
-        idx = np.repeat(lo - np.cumsum(cnt) + cnt, cnt) + np.arange(int(cnt.sum()))
-        key, shared = np.unique(qrep * self.n + self.seq[idx], return_counts=True)
+        keys = []
+        for blk in self.blocks:
+            lo = np.searchsorted(blk, qk * self.n, side="left")
+            hi = np.searchsorted(blk, (qk + 1) * self.n, side="left")
+            cnt = hi - lo
+            qrep = np.repeat(qs, cnt)
+            idx = np.repeat(lo - np.cumsum(cnt) + cnt, cnt) + np.arange(int(cnt.sum()))
+            keys.append(qrep * self.n + blk[idx] % self.n)
+        key, shared = np.unique(np.concatenate(keys), return_counts=True)
         keep = shared >= min_shared
         key, shared = key[keep], shared[keep]
         qq, rr = key // self.n, key % self.n
@@ -420,31 +476,66 @@ class ServeWorkload:
     sizes: np.ndarray      # queries per batch
 
 
+SERVE_FAMILY_BLOCK = 1250  # families per independently seeded block of the reference set
+
+
 def serving(n_fam: int = 20000, per_fam: int = 50, n_batches: int = 200, max_batch: int = 10000,
             top: int = 200, seed: int = 0, workers: int | None = None, sizes=None) -> ServeWorkload:
     """Reference set: n_fam families x per_fam members (ancestors LN(280, 0.6)
-    clipped 30-5000, members Mutation(ancestor, U(0.2, 0.6), 0.03)).  Query
+    clipped 30-5000, members Mutation(ancestor, U(0.2, 0.6), 0.03), drawn in
+    blocks of SERVE_FAMILY_BLOCK families, each from its own seed).  Query
     batches: sizes log-uniform on [1, max_batch] (or the given ``sizes``);
     each query a fresh member of a random family; candidates: references
     sharing >= 2 distinct exact 6-mers, the `top` most-shared first."""
+    global _SERVE_STATE
     rng = rng_for(5, seed)
     La = lognormal_lengths(rng, n_fam, 280.0, 0.6, 30, 5000)
     anc, anc_o = _from_lengths(rng, La)
-    fam = np.repeat(np.arange(n_fam), per_fam)
-    src = anc[gather_segments(anc_o[fam], La[fam])]
-    src_o = np.concatenate([[0], np.cumsum(La[fam])])
-    ref, ref_o = mutate_many(rng, src, src_o, rng.uniform(0.2, 0.6, len(fam)), 0.03)
-    index = KmerIndex(ref, ref_o)
+    blocks = [(seed, b, f0, min(f0 + SERVE_FAMILY_BLOCK, n_fam), per_fam)
+              for b, f0 in enumerate(range(0, n_fam, SERVE_FAMILY_BLOCK))]
+    _SERVE_STATE = (anc, anc_o, La)
+    try:
+        parts = _map_chunks(_serve_ref_block, blocks, workers)
+    finally:
+        _SERVE_STATE = None
+    ref = np.concatenate([p[0] for p in parts])
+    ref_o = np.zeros(n_fam * per_fam + 1, dtype=np.int64)
+    np.cumsum(np.concatenate([np.diff(p[1]) for p in parts]), out=ref_o[1:])
+    n_ref = len(ref_o) - 1
+    _SERVE_STATE = (ref, ref_o, n_ref)
+    try:
+        index = KmerIndex(None, ref_o, 6, blocks=_map_chunks(_serve_index_block, blocks, workers))
+    finally:
+        _SERVE_STATE = None
     drawn = np.exp(rng.uniform(0.0, np.log(max_batch + 1), n_batches)).astype(np.int64).clip(1, max_batch)
     sizes = drawn if sizes is None else np.asarray(sizes, dtype=np.int64)
     n_batches = len(sizes)
-    global _SERVE_STATE
     _SERVE_STATE = (anc, anc_o, La, n_fam, index, top)
     try:
         batches = _map_chunks(_serve_batch, [(seed, b, int(sizes[b])) for b in range(n_batches)], workers)
     finally:
         _SERVE_STATE = None
     return ServeWorkload(ref, ref_o, batches, sizes)
+
+
+def _serve_ref_block(job):
+    """Members of families [f0, f1) of the reference set, per_fam each."""
+    seed, b, f0, f1, per_fam = job
+    anc, anc_o, La = _SERVE_STATE
+    rng = rng_for(7, seed * 100003 + b)
+    fam = np.repeat(np.arange(f0, f1), per_fam)
+    src = anc[gather_segments(anc_o[fam], La[fam])]
+    src_o = np.concatenate([[0], np.cumsum(La[fam])])
+    return mutate_many(rng, src, src_o, rng.uniform(0.2, 0.6, len(fam)), 0.03)
+
+
+def _serve_index_block(job):
+    """Sorted distinct (k-mer, reference) keys of one block's references."""
+    _, _, f0, f1, per_fam = job
+    ref, ref_o, n_ref = _SERVE_STATE
+    r0, r1 = f0 * per_fam, f1 * per_fam
+    km, seq = kmer_sets(ref[ref_o[r0]:ref_o[r1]], ref_o[r0:r1 + 1] - ref_o[r0], 6)
+    return np.sort(km * n_ref + (seq + r0))
 
 
 _SERVE_STATE = None  # shared with the forked workers of serving()
