@@ -254,34 +254,58 @@ SW_API int sw_timing_read_passes(void* stream, double* forward_ms, double* start
  * 64-lane wave; blocks_per_cu sets the
  * persistent grid (1..8; -1 goes back to the occupancy-derived value, which
  * is the default).  A field of 0 (and any other field <= 0) keeps the current
- * value.  Results never depend on these values.
+ * value.
+ * bucket_lanes[b] overrides that rule for length bucket b, the pairs whose
+ * longer sequence has 2^(b-1) + 1 .. 2^b residues (bucket 0: one residue):
+ * 1, 8, 16 or 64 lanes per pair, or 0 for the rule above.  One lane needs
+ * 2^b <= 1024 and 2^b <= 64 rows_per_lane; 8 or 16 lanes need 2^b <= 4096;
+ * 64 lanes fit every bucket.  In sw_set_tuning every entry is applied as
+ * given (0 included), so a caller that only changes the other fields passes
+ * the table sw_get_tuning returned.  Errors: SW_EINVAL for a value outside
+ * these sets, SW_EDEVICE.  Results never depend on any of these values.
  */
+#define SW_NUM_BUCKETS 17
 typedef struct {
     int32_t rows_per_lane;
     int32_t inter_max_len;
     int32_t blocks_per_cu;
     int32_t group16_max_len;
     int32_t group8_max_len;
+    int8_t bucket_lanes[SW_NUM_BUCKETS];
 } sw_tuning;
 SW_API int sw_set_tuning(const sw_tuning* t);
 SW_API int sw_get_tuning(sw_tuning* t);
 
 /*
- * Autotuner: time sw_batch_align (persistent form) on this workload for every
- * candidate kernel shape (rows_per_lane 16/8, inter_max_len 512/768/1024 --
- * the length above which a pair gets a lane group instead of one lane --,
- * group8_max_len 1024/2048, group16_max_len 2048/4096, blocks_per_cu
- * occupancy-derived), `reps`
- * timed runs each, require
- * every shape to give byte-identical results, keep the fastest as the current
- * tuning and report it in *chosen (and its time per call in *best_ms, may be
- * NULL).  Synchronises `stream`; out_dev receives the results.  On error the
- * previous tuning is restored; results that differ between shapes return
- * SW_EDEVICE.
+ * Autotuner of the batching pattern: per length bucket, how many lanes align
+ * one pair (the paper balances its alignment work by the cost of each pair,
+ * m*n, section "Load balancing techniques").
+ * For rows_per_lane 16 and 8 (the occupancy-derived grid), every length
+ * bucket that holds pairs of this workload is timed alone -- the persistent
+ * form over that bucket's pairs, one untimed call then `reps` timed ones --
+ * with each lane count the bucket allows (1, 8, 16, 64), and keeps the
+ * fastest; then the whole workload is timed with each rows_per_lane and its
+ * table, and the faster becomes the current tuning (sw_get_tuning shows it).
+ * Every candidate must give byte-identical results (else SW_EDEVICE and the
+ * previous tuning is restored).  out_dev receives the results of the whole
+ * workload under the chosen tuning.
+ * cache_path (may be NULL): a JSON file of earlier choices, one entry per
+ * (GPU architecture, compute units, blocks per CU, rows_per_lane, gap_open,
+ * gap_extend, bucket) with its lane count and time; buckets found there are
+ * not timed again, new choices are added and the file rewritten.
+ * *chosen receives the tuning, *best_ms (may be NULL) the time of one call of
+ * the whole workload with it, *bucket_trials (may be NULL) the number of
+ * (bucket, lane count) candidates timed in this call (0 when the cache held
+ * every bucket).  Synchronises `stream`.
+ * Errors: SW_EINVAL (null pointer, n_pairs <= 0), SW_EDEVICE (a HIP error or
+ * results that differ between candidates), SW_ENOMEM, and those of
+ * sw_batch_align; an unreadable cache is ignored, an unwritable one is
+ * SW_EINVAL after the tuning is applied.
  */
 SW_API int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs,
                        const int32_t* pairs_dev, int64_t n_pairs, const sw_scoring* scoring,
-                       sw_result* out_dev, void* stream, int32_t reps, sw_tuning* chosen, float* best_ms);
+                       sw_result* out_dev, void* stream, int32_t reps, const char* cache_path,
+                       sw_tuning* chosen, float* best_ms, int32_t* bucket_trials);
 
 /*
  * The scoring matrix (the paper does not name one; BLOSUM62 is used).
@@ -401,6 +425,44 @@ SW_API int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, i
                        const sw_result* aligned_dev, int32_t ani_permille, int32_t cov_permille,
                        sw_identity_result* out_dev, void* stream, uint32_t flags);
 
+/* ------------------------------------------------------------ whole search
+ * The paper's search pipeline on one GPU (section "Protein similarity search
+ * pipeline": discovery of candidate pairs by shared k-mers, their batch
+ * alignment, then the identity and coverage filter that makes the edges of
+ * the similarity graph), formed block by block with the next block made
+ * ready while the current one aligns (section "Pre-blocking").
+ * The queries are cut into contiguous blocks of block_queries queries (0: a
+ * quarter of them).  For each block, sw_discover's pairs (k, min_shared,
+ * mode as there; the mode filters use the global query index) are handed on
+ * the device to the aligner (persistent form) and to sw_identity
+ * (ani_permille, cov_permille as there), and the pairs it keeps are appended
+ * to the outputs: edges_dev int32[2 * edge_cap] (query, reference),
+ * edge_results_dev sw_result[edge_cap], edge_ident_dev
+ * sw_identity_result[edge_cap], in no particular order (the set is exact).
+ * Discovery runs on one internal stream and the alignment and the filter on
+ * another, so the discovery of block b+1 overlaps the alignment of block b;
+ * two sets of block buffers, kept by the library and grown to the largest
+ * block, bound the memory.  Both streams start after the work already
+ * enqueued on `stream`; the call returns when everything is done.
+ * *stats receives the candidates, the edges (all of them, also when more
+ * than edge_cap: then only edge_cap are written and the call returns
+ * SW_ENOMEM) and the number of blocks.  Calls on one device run one at a
+ * time.  Errors: those of sw_discover, sw_align_sets and sw_identity.
+ */
+typedef struct {
+    int64_t candidates; /* pairs discovery found */
+    int64_t edges;      /* pairs the filter kept */
+    int32_t blocks;     /* query blocks */
+    int32_t reserved;
+} sw_search_stats;
+
+SW_API int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                     const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r, int32_t k,
+                     int32_t min_shared, int32_t mode, const sw_scoring* scoring, int32_t ani_permille,
+                     int32_t cov_permille, int64_t block_queries, int32_t* edges_dev,
+                     sw_result* edge_results_dev, sw_identity_result* edge_ident_dev, int64_t edge_cap,
+                     sw_search_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching against a reference set resident in HBM.  The server
  * keeps `max_slots` HIP streams, each with its own alignment workspace, and an
@@ -473,10 +535,13 @@ SW_API size_t sw_server_request_bytes(int64_t n_residues, int64_t n_q, int64_t n
  * in flight, then free the server. */
 SW_API int sw_server_destroy(sw_server* server);
 
-/* Text of a status code; never NULL. */
+/* Error reporting of the driver (section "Software stack and parallelism":
+ * the layer between the application and the kernels).  Text of a status
+ * code; never NULL. */
 SW_API const char* sw_strerror(int status);
 
-/* Text of the last HIP runtime error seen by the library on this thread. */
+/* The same driver's record of the last HIP runtime error (or refusal with a
+ * message) seen by the library on this thread. */
 SW_API const char* sw_last_device_error(void);
 
 #ifdef __cplusplus

@@ -39,7 +39,7 @@ EXPORTS = ("sw_packed_bytes", "sw_pack", "sw_batch_align", "sw_align_sets", "sw_
            "sw_timing_read_passes", "sw_set_tuning",
            "sw_get_tuning", "sw_autotune", "sw_matrix", "sw_strerror", "sw_last_device_error", "sw_server_create",
            "sw_server_submit", "sw_server_poll", "sw_server_wait", "sw_server_stats",
-           "sw_server_request_bytes", "sw_server_destroy", "sw_discover", "sw_identity")
+           "sw_server_request_bytes", "sw_server_destroy", "sw_discover", "sw_identity", "sw_search")
 
 DISCOVER_ALL = 0
 DISCOVER_UPPER = 1
@@ -61,10 +61,21 @@ class Scoring(ctypes.Structure):
                 ("gap_extend", ctypes.c_int32)]
 
 
+NUM_BUCKETS = 17
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("inter_max_len", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("group16_max_len", ctypes.c_int32),
-                ("group8_max_len", ctypes.c_int32)]
+                ("group8_max_len", ctypes.c_int32), ("bucket_lanes", ctypes.c_int8 * NUM_BUCKETS)]
+
+
+class SearchStats(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int64), ("edges", ctypes.c_int64), ("blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+
 
 
 _lib = None
@@ -121,7 +132,14 @@ def lib():
         L.sw_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.sw_autotune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.c_int64, ctypes.POINTER(Scoring), ctypes.c_void_p, ctypes.c_void_p,
-                                  ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float)]
+                                  ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(Tuning),
+                                  ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
+        L.sw_search.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.POINTER(Scoring), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.POINTER(SearchStats), ctypes.c_void_p]
+
         L.sw_matrix.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_char_p]
         L.sw_identity.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -284,39 +302,79 @@ def timing_read_passes(stream=None):
     return f.value, s.value, n.value
 
 
+def _tuning_dict(t) -> dict:
+    return {"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
+            "blocks_per_cu": t.blocks_per_cu, "group16_max_len": t.group16_max_len,
+            "group8_max_len": t.group8_max_len, "bucket_lanes": list(t.bucket_lanes)}
+
+
 def set_tuning(rows_per_lane: int = 0, inter_max_len: int = 0, blocks_per_cu: int = 0,
-               group16_max_len: int = 0, group8_max_len: int = 0):
-    """0 keeps a field; blocks_per_cu -1 returns to the occupancy-derived grid."""
+               group16_max_len: int = 0, group8_max_len: int = 0, bucket_lanes=None):
+    """0 keeps a field; blocks_per_cu -1 returns to the occupancy-derived grid;
+    bucket_lanes (17 lane counts, 0 = the threshold rule) is applied as given
+    (all zeros when omitted)."""
+    lanes = (ctypes.c_int8 * NUM_BUCKETS)(*(bucket_lanes or [0] * NUM_BUCKETS))
     _check(lib().sw_set_tuning(ctypes.byref(Tuning(rows_per_lane, inter_max_len, blocks_per_cu,
-                                                   group16_max_len, group8_max_len))), "sw_set_tuning")
+                                                   group16_max_len, group8_max_len, lanes))), "sw_set_tuning")
 
 
 def get_tuning() -> dict:
     t = Tuning()
     _check(lib().sw_get_tuning(ctypes.byref(t)), "sw_get_tuning")
-    return {"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
-            "blocks_per_cu": t.blocks_per_cu, "group16_max_len": t.group16_max_len,
-            "group8_max_len": t.group8_max_len}
+    return _tuning_dict(t)
 
 
 def autotune(packed, offsets, pairs, gap_open: int = 11, gap_extend: int = 1, reps: int = 3,
-             out=None, stream=None):
-    """Pick and keep the fastest kernel shape for this workload (results must
-    be identical across shapes).  Returns (tuning dict, ms per call)."""
+             out=None, stream=None, cache_path=None):
+    """Per length bucket, pick and keep the fastest lane count for this
+    workload (results must be identical across candidates), with an optional
+    JSON cache of earlier choices.  Returns (tuning dict, ms per call of the
+    whole workload, bucket candidates timed)."""
     import torch
     n_pairs = int(pairs.shape[0])
     if out is None:
         out = torch.empty((n_pairs, 5), dtype=torch.int32, device=pairs.device)
     t = Tuning()
     ms = ctypes.c_float()
+    trials = ctypes.c_int32()
     sc = Scoring(0, int(gap_open), int(gap_extend))
+    path = None if cache_path is None else str(cache_path).encode()
     _check(lib().sw_autotune(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
                              int(offsets.numel()) - 1, ctypes.c_void_p(pairs.data_ptr()), n_pairs,
                              ctypes.byref(sc), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), int(reps),
-                             ctypes.byref(t), ctypes.byref(ms)), "sw_autotune")
-    return ({"rows_per_lane": t.rows_per_lane, "inter_max_len": t.inter_max_len,
-             "blocks_per_cu": t.blocks_per_cu, "group16_max_len": t.group16_max_len,
-             "group8_max_len": t.group8_max_len}, float(ms.value))
+                             path, ctypes.byref(t), ctypes.byref(ms), ctypes.byref(trials)), "sw_autotune")
+    return _tuning_dict(t), float(ms.value), int(trials.value)
+
+
+def search(q_packed, q_offsets, r_packed, r_offsets, k: int = 6, min_shared: int = 2, mode: int = 0,
+           gap_open: int = 11, gap_extend: int = 1, ani_permille: int = 300, cov_permille: int = 700,
+           block_queries: int = 0, edge_cap=None, stream=None):
+    """The whole search on the device (sw_search): discovery, alignment and
+    the identity / coverage filter, block by block.  Returns (edges int32
+    [n, 2], alignment results int32 [n, 5], identity records int32 [n, 4],
+    stats dict); the edges come in no particular order."""
+    import torch
+    dev = q_packed.device
+    n_q = int(q_offsets.numel()) - 1
+    cap = int(edge_cap) if edge_cap is not None else max(1024, 32 * n_q)
+    sc = Scoring(0, int(gap_open), int(gap_extend))
+    while True:
+        e = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        r = torch.empty((cap, 5), dtype=torch.int32, device=dev)
+        i = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+        st = SearchStats()
+        rc = lib().sw_search(ctypes.c_void_p(q_packed.data_ptr()), ctypes.c_void_p(q_offsets.data_ptr()), n_q,
+                             ctypes.c_void_p(r_packed.data_ptr()), ctypes.c_void_p(r_offsets.data_ptr()),
+                             int(r_offsets.numel()) - 1, int(k), int(min_shared), int(mode), ctypes.byref(sc),
+                             int(ani_permille), int(cov_permille), int(block_queries), ctypes.c_void_p(e.data_ptr()),
+                             ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(i.data_ptr()), cap, ctypes.byref(st),
+                             _stream_ptr(stream))
+        if rc == SW_ENOMEM and edge_cap is None and st.edges > cap:
+            cap = int(st.edges)
+            continue
+        _check(rc, "sw_search")
+        n = int(st.edges)
+        return e[:n], r[:n], i[:n], {"candidates": int(st.candidates), "edges": n, "blocks": int(st.blocks)}
 
 
 def matrix():

@@ -35,5 +35,9 @@ struct IdentArgs {
 };
 
 hipError_t launch_identity(const IdentArgs& a, int blocks, hipStream_t stream);
+// the kept pairs (keep == 1) with their records, appended at *count
+hipError_t launch_edges(const int32_t* pairs, const sw_result* res, const sw_identity_result* id, int64_t n,
+                        int32_t* e_pairs, sw_result* e_res, sw_identity_result* e_id, int64_t cap,
+                        unsigned long long* count, hipStream_t stream);
 
 }  // namespace swk

@@ -51,7 +51,7 @@ int ceil_log2(int64_t x)
     return b;
 }
 
-Ordering make_ordering(int R, int inter_max, int group8_max, int group16_max)
+Ordering make_ordering(int R, int group8_max, int group16_max, const int8_t* bucket_lanes)
 {
     struct Key {
         int cell;
@@ -62,15 +62,14 @@ Ordering make_ordering(int R, int inter_max, int group8_max, int group16_max)
     };
     std::vector<Key> keys;
     keys.reserve(kNumCells);
-    const int smax = (inter_max + R - 1) / R, cmax = (inter_max + 7) / 8;
+    // every one-lane cell by its cost (cells no pair can reach stay empty)
     for (int s = 1; s <= kMaxInterStrips; ++s)
         for (int c = 1; c <= kMaxInterChunks; ++c) {
             Key k;
             k.cell = (s - 1) * kMaxInterChunks + (c - 1);
             k.kind = 1;
             k.bucket = ceil_log2(std::max<int64_t>((int64_t)s * R, 8 * c));
-            const bool reachable = s <= smax && c <= cmax;
-            k.cost = reachable ? (int64_t)s * c : -1;
+            k.cost = (int64_t)s * c;
             k.s = s;
             k.c = c;
             keys.push_back(k);
@@ -79,8 +78,7 @@ Ordering make_ordering(int R, int inter_max, int group8_max, int group16_max)
         for (int cb = 0; cb < kWideCostBins; ++cb) {
             Key k;
             k.cell = kInterCells + b * kWideCostBins + cb;
-            const int64_t len = (int64_t)1 << b;
-            k.kind = len <= std::min(group8_max, kMaxP16Len) ? 8 : len <= std::min(group16_max, kMaxP16Len) ? 16 : 64;
+            k.kind = bucket_group_kind(b, bucket_lanes[b], group8_max, group16_max);
             k.bucket = b;
             k.cost = cb;
             k.s = k.c = 0;
@@ -252,21 +250,33 @@ struct Device {
     int group16_max = kDefaultGroup16Max;
     int group8_max = kDefaultGroup8Max;
     int bpc_user = 0;  // 0: occupancy-derived
+    int8_t bucket_lanes[kNumLenBuckets] = {};  // per-bucket overrides (0: the threshold rule)
     Ordering ord;
     int32_t* rank_cell_persistent = nullptr;  // file-scope device arrays (device_statics)
     int32_t* rank_cell_plain = nullptr;
     int32_t* err = nullptr;
     void* static_ws = nullptr;                // kStaticWsBytes (sw_align_sets_static)
     hipStream_t capture_stream = nullptr;     // created by the first graph capture
+    // sw_search: its discovery and alignment streams, events and the two
+    // sets of per-block buffers (kept, grown to the largest block)
+    hipStream_t search_stream[2] = {nullptr, nullptr};
+    hipEvent_t search_ev[5] = {};  // start, discovery done x2, alignment done x2
+    int64_t search_cap = 0;
+    int32_t* search_pairs[2] = {nullptr, nullptr};
+    sw_result* search_res[2] = {nullptr, nullptr};
+    sw_identity_result* search_id[2] = {nullptr, nullptr};
+    unsigned long long* search_count = nullptr;
+    unsigned long long* search_count_host = nullptr;
     std::map<hipStream_t, std::unique_ptr<Workspace>> ws;
 };
 
 std::mutex g_mutex;
+std::mutex g_search_mutex;  // one sw_search at a time (they share the device's search streams)
 std::map<int, std::unique_ptr<Device>> g_devices;
 
 int upload_ordering(Device& d)
 {
-    d.ord = make_ordering(d.R, d.inter_max, d.group8_max, d.group16_max);
+    d.ord = make_ordering(d.R, d.group8_max, d.group16_max, d.bucket_lanes);
     HIP_TRY(hipMemcpy(d.rank_cell_persistent, d.ord.rank_cell_persistent.data(), sizeof(int32_t) * kNumCells,
                       hipMemcpyHostToDevice),
             "upload ordering");
@@ -480,6 +490,105 @@ int timing_events(Workspace& w, std::pair<hipEvent_t, hipEvent_t>* ev)
     return SW_OK;
 }
 
+// Whether a per-bucket lane count is allowed (0 is the threshold rule):
+// one lane holds at most 64 rows_per_lane rows and 1024 columns, 8- and
+// 16-lane groups at most kMaxP16Len residues.
+bool lanes_allowed(int bucket, int lanes, int R)
+{
+    const int64_t len = (int64_t)1 << bucket;
+    switch (lanes) {
+    case 0: return true;
+    case 1: return len <= kMaxInterLen && len <= (int64_t)kMaxInterStrips * R;
+    case 8:
+    case 16: return len <= kMaxP16Len;
+    case 64: return true;
+    default: return false;
+    }
+}
+
+bool bucket_lanes_valid(const int8_t* lanes, int R)
+{
+    for (int b = 0; b < kNumLenBuckets; ++b)
+        if (!lanes_allowed(b, lanes[b], R)) return false;
+    return true;
+}
+
+// One autotuner choice: the device and scoring it was made for, the length
+// bucket and its lane count, and the time of the bucket's pairs with it.
+struct TuneEntry {
+    std::string arch;
+    int cus, blocks_per_cu, rows_per_lane, gap_open, gap_extend, bucket, lanes;
+    float ms;
+};
+
+bool same_key(const TuneEntry& a, const TuneEntry& b)
+{
+    return a.arch == b.arch && a.cus == b.cus && a.blocks_per_cu == b.blocks_per_cu &&
+           a.rows_per_lane == b.rows_per_lane && a.gap_open == b.gap_open && a.gap_extend == b.gap_extend &&
+           a.bucket == b.bucket;
+}
+
+const TuneEntry* find_tune_entry(const std::vector<TuneEntry>& c, const TuneEntry& key)
+{
+    for (const auto& e : c)
+        if (same_key(e, key)) return &e;
+    return nullptr;
+}
+
+void put_tune_entry(std::vector<TuneEntry>& c, const TuneEntry& e)
+{
+    for (auto& x : c)
+        if (same_key(x, e)) {
+            x = e;
+            return;
+        }
+    c.push_back(e);
+}
+
+// The cache file is JSON with one entry per line, as write_tune_cache
+// writes it; lines that do not parse as an entry are skipped.
+std::vector<TuneEntry> read_tune_cache(const char* path)
+{
+    std::vector<TuneEntry> out;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return out;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char arch[64] = {0};
+        TuneEntry e;
+        if (std::sscanf(line,
+                        " {\"arch\": \"%63[^\"]\", \"cus\": %d, \"blocks_per_cu\": %d, \"rows_per_lane\": %d, "
+                        "\"gap_open\": %d, \"gap_extend\": %d, \"bucket\": %d, \"lanes\": %d, \"ms\": %f}",
+                        arch, &e.cus, &e.blocks_per_cu, &e.rows_per_lane, &e.gap_open, &e.gap_extend, &e.bucket,
+                        &e.lanes, &e.ms) == 9 &&
+            e.bucket >= 0 && e.bucket < kNumLenBuckets) {
+            e.arch = arch;
+            out.push_back(e);
+        }
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool write_tune_cache(const char* path, const std::vector<TuneEntry>& c)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\"sw_autotune_cache\": 1, \"entries\": [\n");
+    for (size_t k = 0; k < c.size(); ++k) {
+        const TuneEntry& e = c[k];
+        std::fprintf(f,
+                     " {\"arch\": \"%s\", \"cus\": %d, \"blocks_per_cu\": %d, \"rows_per_lane\": %d, "
+                     "\"gap_open\": %d, \"gap_extend\": %d, \"bucket\": %d, \"lanes\": %d, \"ms\": %.4f}%s\n",
+                     e.arch.c_str(), e.cus, e.blocks_per_cu, e.rows_per_lane, e.gap_open, e.gap_extend, e.bucket,
+                     e.lanes, e.ms, k + 1 < c.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
 int read_and_clear_errors(Device& d, hipStream_t stream)
 {
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
@@ -576,6 +685,7 @@ void fill_args(Args& a, const Device& d, const WsView& v, const void* q_packed_d
     a.inter_max_len = d.inter_max;
     a.group16_max_len = d.group16_max;
     a.group8_max_len = d.group8_max;
+    std::memcpy(a.bucket_kind, d.bucket_lanes, sizeof(a.bucket_kind));
 }
 
 // Where the device arrays of a call come from.
@@ -767,78 +877,46 @@ int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n
     return SW_OK;
 }
 
-}  // namespace
+// ------------------------------------------------------------------ discovery phases
+constexpr int kDiscoverNothing = 1;  // discover_check: valid, and an empty set makes no pairs
 
-extern "C" {
-
-int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
-                  const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
-                  const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
+int discover_check(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                   const int64_t* r_offsets_dev, int64_t n_r, int32_t k, int32_t min_shared, int32_t mode)
 {
-    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
-                      out_dev, WsMode::library, nullptr, 0, stream, flags);
-}
-
-int sw_align_sets_static(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
-                         const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev,
-                         int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
-{
-    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
-                      out_dev, WsMode::fixed, nullptr, 0, stream, flags);
-}
-
-int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
-                     const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
-                     const sw_scoring* scoring, sw_result* out_dev, void* workspace_dev, size_t workspace_bytes,
-                     void* stream, uint32_t flags)
-{
-    if (!workspace_dev) return SW_EINVAL;
-    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
-                      out_dev, WsMode::caller, workspace_dev, workspace_bytes, stream, flags);
-}
-
-int sw_workspace_size(int64_t n_pairs, int64_t max_len, size_t* bytes)
-{
-    if (!bytes || n_pairs < 0 || max_len < 0) return SW_EINVAL;
-    *bytes = 0;
-    if (max_len > SW_MAX_SEQ_LEN) return SW_ERANGE;
-    if (n_pairs > (int64_t)0x7FFFFFFF - 64) return SW_ERANGE;
-    std::lock_guard<std::mutex> lock(g_mutex);
-    Device* d = nullptr;
-    int rc = get_device(&d);
-    if (rc) return rc;
-    const int64_t grid = (int64_t)d->n_cu * blocks_per_cu(*d);
-    *bytes = ws_head_bytes(n_pairs) + (size_t)grid * sizeof(uint32_t) * (size_t)slot_words_for(max_len);
-    return SW_OK;
-}
-
-int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs, const int32_t* pairs_dev,
-                   int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
-{
-    return sw_align_sets(packed_dev, offsets_dev, n_seqs, packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs,
-                         scoring, out_dev, stream, flags);
-}
-
-int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
-                const int64_t* r_offsets_dev, int64_t n_r, int32_t k, int32_t min_shared, int32_t mode,
-                int32_t* pairs_out_dev, int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found,
-                size_t table_budget_bytes, void* stream_)
-{
-    if (!n_found) return SW_EINVAL;
-    *n_found = 0;
     if (k < 1 || k > kKmerMaxK || min_shared < 1 || mode < SW_DISCOVER_ALL || mode > SW_DISCOVER_PARITY ||
-        n_q < 0 || n_r < 0 || out_cap < 0)
+        n_q < 0 || n_r < 0)
         return SW_EINVAL;
     if (mode != SW_DISCOVER_ALL && n_q != n_r) return SW_EINVAL;
-    if (out_cap > 0 && !pairs_out_dev) return SW_EINVAL;
     if (n_q > (int64_t)0x7FFFFFFF || n_r > (int64_t)0x7FFFFFFF) return SW_ERANGE;
-    if (n_q == 0 || n_r == 0) return SW_OK;
+    if (n_q == 0 || n_r == 0) return kDiscoverNothing;
     if (!q_packed_dev || !q_offsets_dev || !r_packed_dev || !r_offsets_dev) return SW_EINVAL;
     if ((reinterpret_cast<uintptr_t>(q_packed_dev) | reinterpret_cast<uintptr_t>(r_packed_dev)) & 15u)
         return SW_EINVAL;
-    hipStream_t stream = (hipStream_t)stream_;
+    return SW_OK;
+}
 
-    std::lock_guard<std::mutex> lock(g_mutex);
+// State after the shared steps of discovery: the query table and the number
+// of k-mer matches (sum over query entries of their reference-list length).
+struct DiscoverPrep {
+    KmerSide Q, R;
+    uint64_t* set_q = nullptr;
+    int64_t cap_q = 0;
+    int64_t products = 0;
+};
+
+// A contiguous query range [lo, hi) joined with one pair table of `cap` slots.
+struct DiscoverRange {
+    int64_t lo, hi, cap;
+};
+
+// Steps 1-4 of discovery on `stream` (its workspace): k-mer windows per set
+// (offsets checked before any kernel reads residues), the distinct
+// (sequence, k-mer) tables, the reference list of every k-mer, the count of
+// k-mer matches.  Called with g_mutex held.
+int discover_prepare(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                     const int64_t* r_offsets_dev, int64_t n_r, int k, hipStream_t stream, DiscoverSpace** xout,
+                     DiscoverPrep* prep)
+{
     Device* dp = nullptr;
     int rc = get_device(&dp);
     if (rc) return rc;
@@ -846,6 +924,7 @@ int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     if ((rc = get_workspace(*dp, stream, &wp))) return rc;
     if (!wp->discover) wp->discover.reset(new DiscoverSpace());
     DiscoverSpace& x = *wp->discover;
+    *xout = &x;
     if (!x.counters) {
         if ((rc = grow(&x.counters, kKmNumCounters))) return rc;
         HIP_TRY(hipHostMalloc((void**)&x.host, sizeof(uint64_t) * kKmNumCounters), "hipHostMalloc");
@@ -907,67 +986,288 @@ int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     HIP_TRY(launch_kmer_scan(x.kcount, x.kstart, kspace, x.tile_sums, stream), "discover launch");
     HIP_TRY(launch_kmer_scatter(x.set_r, cap_r, x.kstart, x.kcount, x.rlist, stream), "discover launch");
 
-    // 4. size the pair table by the number of k-mer matches, then count
+    // 4. the number of k-mer matches, which sizes the pair tables
     HIP_TRY(launch_kmer_products(set_q, cap_q, x.kstart, x.counters, stream), "discover launch");
     if ((rc = read_counters(x, stream))) return rc;
-    const int64_t products = (int64_t)x.host[kKmProducts];
+    prep->Q = Q;
+    prep->R = R;
+    prep->set_q = set_q;
+    prep->cap_q = cap_q;
+    prep->products = (int64_t)x.host[kKmProducts];
+    return SW_OK;
+}
+
+// Matches per query (host copy), for cutting the queries into ranges.
+int discover_query_products(DiscoverSpace& x, const DiscoverPrep& prep, int64_t n_q, hipStream_t stream,
+                            std::vector<uint64_t>* qp)
+{
+    int rc;
+    if (n_q > x.qprod_cap) {
+        if ((rc = grow(&x.qprod, n_q))) return x.qprod_cap = 0, rc;
+        x.qprod_cap = n_q;
+    }
+    HIP_TRY(hipMemsetAsync(x.qprod, 0, sizeof(uint64_t) * n_q, stream), "clear counts");
+    HIP_TRY(launch_kmer_query_products(prep.set_q, prep.cap_q, x.kstart, x.qprod, stream), "discover launch");
+    qp->resize((size_t)n_q);
+    HIP_TRY(hipMemcpyAsync(qp->data(), x.qprod, sizeof(uint64_t) * n_q, hipMemcpyDeviceToHost, stream),
+            "read counts");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return SW_OK;
+}
+
+// Contiguous query ranges of at most per_range matches (a query above it gets
+// a range of its own) and, when max_queries > 0, at most that many queries.
+std::vector<DiscoverRange> split_ranges(const std::vector<uint64_t>& qp, int64_t per_range, int64_t max_queries)
+{
+    std::vector<DiscoverRange> out;
+    const int64_t n_q = (int64_t)qp.size();
+    int64_t lo = 0, acc = 0;
+    for (int64_t q = 0; q < n_q; ++q) {
+        if (q > lo && (acc + (int64_t)qp[q] > per_range || (max_queries > 0 && q - lo >= max_queries))) {
+            out.push_back({lo, q, pow2_at_least(2 * acc)});
+            lo = q;
+            acc = 0;
+        }
+        acc += (int64_t)qp[q];
+    }
+    out.push_back({lo, n_q, pow2_at_least(2 * acc)});
+    return out;
+}
+
+// Step 5 for one query range: join it with the reference lists in a pair
+// table of r.cap slots and append its pairs at or above the threshold to
+// pairs_out (counter kKmOut; at most out_cap written).
+int discover_join(DiscoverSpace& x, const DiscoverPrep& prep, int mode, int min_shared, const DiscoverRange& r,
+                  int32_t* pairs_out, int32_t* shared_out, int64_t out_cap, hipStream_t stream)
+{
+    int rc;
+    if (r.cap > x.pcap) {
+        if ((rc = grow(&x.pkeys, r.cap)) || (rc = grow(&x.pcount, r.cap))) return x.pcap = 0, rc;
+        x.pcap = r.cap;
+    }
+    HIP_TRY(hipMemsetAsync(x.pkeys, 0xFF, sizeof(uint64_t) * r.cap, stream), "clear table");
+    HIP_TRY(hipMemsetAsync(x.pcount, 0, sizeof(int32_t) * r.cap, stream), "clear table");
+    HIP_TRY(launch_kmer_join(prep.set_q, prep.cap_q, x.kstart, x.rlist, mode, r.lo, r.hi, x.pkeys, x.pcount, r.cap,
+                             x.counters, stream),
+            "discover launch");
+    HIP_TRY(launch_kmer_compact(x.pkeys, x.pcount, r.cap, min_shared, pairs_out, shared_out, out_cap, x.counters,
+                                stream),
+            "discover launch");
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_align_sets(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                  const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+                  const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
+{
+    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
+                      out_dev, WsMode::library, nullptr, 0, stream, flags);
+}
+
+int sw_align_sets_static(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q,
+                         const void* r_packed_dev, const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev,
+                         int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
+{
+    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
+                      out_dev, WsMode::fixed, nullptr, 0, stream, flags);
+}
+
+int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                     const int64_t* r_offsets_dev, int64_t n_r, const int32_t* pairs_dev, int64_t n_pairs,
+                     const sw_scoring* scoring, sw_result* out_dev, void* workspace_dev, size_t workspace_bytes,
+                     void* stream, uint32_t flags)
+{
+    if (!workspace_dev) return SW_EINVAL;
+    return align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, pairs_dev, n_pairs, scoring,
+                      out_dev, WsMode::caller, workspace_dev, workspace_bytes, stream, flags);
+}
+
+int sw_workspace_size(int64_t n_pairs, int64_t max_len, size_t* bytes)
+{
+    if (!bytes || n_pairs < 0 || max_len < 0) return SW_EINVAL;
+    *bytes = 0;
+    if (max_len > SW_MAX_SEQ_LEN) return SW_ERANGE;
+    if (n_pairs > (int64_t)0x7FFFFFFF - 64) return SW_ERANGE;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Device* d = nullptr;
+    int rc = get_device(&d);
+    if (rc) return rc;
+    const int64_t grid = (int64_t)d->n_cu * blocks_per_cu(*d);
+    *bytes = ws_head_bytes(n_pairs) + (size_t)grid * sizeof(uint32_t) * (size_t)slot_words_for(max_len);
+    return SW_OK;
+}
+
+int sw_batch_align(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs, const int32_t* pairs_dev,
+                   int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream, uint32_t flags)
+{
+    return sw_align_sets(packed_dev, offsets_dev, n_seqs, packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs,
+                         scoring, out_dev, stream, flags);
+}
+
+int sw_discover(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+                const int64_t* r_offsets_dev, int64_t n_r, int32_t k, int32_t min_shared, int32_t mode,
+                int32_t* pairs_out_dev, int32_t* shared_out_dev, int64_t out_cap, int64_t* n_found,
+                size_t table_budget_bytes, void* stream_)
+{
+    if (!n_found) return SW_EINVAL;
+    *n_found = 0;
+    if (out_cap < 0 || (out_cap > 0 && !pairs_out_dev)) return SW_EINVAL;
+    int rc = discover_check(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, k, min_shared, mode);
+    if (rc) return rc == kDiscoverNothing ? SW_OK : rc;
+    hipStream_t stream = (hipStream_t)stream_;
+
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DiscoverSpace* xp = nullptr;
+    DiscoverPrep prep;
+    if ((rc = discover_prepare(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, k, stream, &xp,
+                               &prep)))
+        return rc;
+    DiscoverSpace& x = *xp;
     constexpr int64_t kSlotBytes = sizeof(uint64_t) + sizeof(int32_t);
     // query ranges, each joined with its own pair table: one range unless the
     // whole table would exceed the budget
-    std::vector<std::pair<int64_t, int64_t>> ranges;  // [q_lo, q_hi), table slots
-    std::vector<int64_t> range_cap;
-    if (table_budget_bytes == 0 || pow2_at_least(2 * products) * kSlotBytes <= (int64_t)table_budget_bytes) {
-        ranges.emplace_back(0, n_q);
-        range_cap.push_back(pow2_at_least(2 * products));
+    std::vector<DiscoverRange> ranges;
+    if (table_budget_bytes == 0 || pow2_at_least(2 * prep.products) * kSlotBytes <= (int64_t)table_budget_bytes) {
+        ranges.push_back({0, n_q, pow2_at_least(2 * prep.products)});
     } else {
-        if (n_q > x.qprod_cap) {
-            if ((rc = grow(&x.qprod, n_q))) return x.qprod_cap = 0, rc;
-            x.qprod_cap = n_q;
-        }
-        HIP_TRY(hipMemsetAsync(x.qprod, 0, sizeof(uint64_t) * n_q, stream), "clear counts");
-        HIP_TRY(launch_kmer_query_products(set_q, cap_q, x.kstart, x.qprod, stream), "discover launch");
-        std::vector<uint64_t> qp((size_t)n_q);
-        HIP_TRY(hipMemcpyAsync(qp.data(), x.qprod, sizeof(uint64_t) * n_q, hipMemcpyDeviceToHost, stream),
-                "read counts");
-        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        std::vector<uint64_t> qp;
+        if ((rc = discover_query_products(x, prep, n_q, stream, &qp))) return rc;
         // the largest match count whose table (twice as many slots, a power
         // of two) fits the budget; a query above it gets a range of its own
         int64_t slots = 256;
         while (slots * 2 * kSlotBytes <= (int64_t)table_budget_bytes) slots *= 2;
-        const int64_t per_range = std::max<int64_t>(slots / 2, 1);
-        int64_t lo = 0, acc = 0;
-        for (int64_t q = 0; q < n_q; ++q) {
-            if (q > lo && acc + (int64_t)qp[q] > per_range) {
-                ranges.emplace_back(lo, q);
-                range_cap.push_back(pow2_at_least(2 * acc));
-                lo = q;
-                acc = 0;
-            }
-            acc += (int64_t)qp[q];
-        }
-        ranges.emplace_back(lo, n_q);
-        range_cap.push_back(pow2_at_least(2 * acc));
+        ranges = split_ranges(qp, std::max<int64_t>(slots / 2, 1), 0);
     }
-    const int64_t pcap = *std::max_element(range_cap.begin(), range_cap.end());
-    if (pcap > x.pcap) {
-        if ((rc = grow(&x.pkeys, pcap)) || (rc = grow(&x.pcount, pcap))) return x.pcap = 0, rc;
-        x.pcap = pcap;
-    }
-    for (size_t b = 0; b < ranges.size(); ++b) {
-        const int64_t cap_b = range_cap[b];
-        HIP_TRY(hipMemsetAsync(x.pkeys, 0xFF, sizeof(uint64_t) * cap_b, stream), "clear table");
-        HIP_TRY(hipMemsetAsync(x.pcount, 0, sizeof(int32_t) * cap_b, stream), "clear table");
-        HIP_TRY(launch_kmer_join(set_q, cap_q, x.kstart, x.rlist, mode, ranges[b].first, ranges[b].second, x.pkeys,
-                                 x.pcount, cap_b, x.counters, stream),
-                "discover launch");
-        // 5. pairs at or above the threshold (appended after earlier ranges')
-        HIP_TRY(launch_kmer_compact(x.pkeys, x.pcount, cap_b, min_shared, pairs_out_dev, shared_out_dev, out_cap,
-                                    x.counters, stream),
-                "discover launch");
-    }
+    for (const DiscoverRange& r : ranges)
+        if ((rc = discover_join(x, prep, mode, min_shared, r, pairs_out_dev, shared_out_dev, out_cap, stream)))
+            return rc;
     if ((rc = read_counters(x, stream))) return rc;
     *n_found = (int64_t)x.host[kKmOut];
     return *n_found > out_cap ? SW_ENOMEM : SW_OK;
+}
+
+int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
+              const int64_t* r_offsets_dev, int64_t n_r, int32_t k, int32_t min_shared, int32_t mode,
+              const sw_scoring* scoring, int32_t ani_permille, int32_t cov_permille, int64_t block_queries,
+              int32_t* edges_dev, sw_result* edge_results_dev, sw_identity_result* edge_ident_dev, int64_t edge_cap,
+              sw_search_stats* stats, void* stream_)
+{
+    if (!stats || !scoring || edge_cap < 0 || block_queries < 0) return SW_EINVAL;
+    std::memset(stats, 0, sizeof(*stats));
+    if (edge_cap > 0 && (!edges_dev || !edge_results_dev || !edge_ident_dev)) return SW_EINVAL;
+    if (scoring->matrix_id != 0 || scoring->gap_open < 1 || scoring->gap_open > (1 << 20) ||
+        scoring->gap_extend < 0 || scoring->gap_extend > scoring->gap_open)
+        return SW_EINVAL;
+    if (ani_permille < 0 || ani_permille > 1000 || cov_permille < 0 || cov_permille > 1000) return SW_EINVAL;
+    int rc = discover_check(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, k, min_shared, mode);
+    if (rc) return rc == kDiscoverNothing ? SW_OK : rc;
+    hipStream_t caller = (hipStream_t)stream_;
+    std::lock_guard<std::mutex> search_lock(g_search_mutex);
+
+    Device* dp = nullptr;
+    DiscoverSpace* xp = nullptr;
+    DiscoverPrep prep;
+    std::vector<uint64_t> qp;
+    hipStream_t sd = nullptr, sa = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        if ((rc = get_device(&dp))) return rc;
+        Device& d = *dp;
+        for (auto& st : d.search_stream)
+            if (!st) HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+        for (auto& ev : d.search_ev)
+            if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+        if (!d.search_count) {
+            if ((rc = grow(&d.search_count, 1))) return rc;
+            HIP_TRY(hipHostMalloc((void**)&d.search_count_host, sizeof(unsigned long long)), "hipHostMalloc");
+        }
+        sd = d.search_stream[0];
+        sa = d.search_stream[1];
+        // both streams start after the caller's earlier work
+        HIP_TRY(hipEventRecord(d.search_ev[0], caller), "hipEventRecord");
+        HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[0], 0), "hipStreamWaitEvent");
+        HIP_TRY(hipStreamWaitEvent(sa, d.search_ev[0], 0), "hipStreamWaitEvent");
+        HIP_TRY(hipMemsetAsync(d.search_count, 0, sizeof(unsigned long long), sa), "clear counter");
+        if ((rc = discover_prepare(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, k, sd, &xp,
+                                   &prep)))
+            return rc;
+        if ((rc = discover_query_products(*xp, prep, n_q, sd, &qp))) return rc;
+    }
+    Device& d = *dp;
+    DiscoverSpace& x = *xp;
+    // query blocks: block_queries queries each (0: a quarter of the queries);
+    // a block's pairs are at most its k-mer matches
+    const int64_t per_block = block_queries > 0 ? block_queries : std::max<int64_t>((n_q + 3) / 4, 1);
+    const std::vector<DiscoverRange> ranges = split_ranges(qp, (int64_t)1 << 62, per_block);
+    int64_t need = 1;
+    for (const DiscoverRange& r : ranges) {
+        int64_t m = 0;
+        for (int64_t q = r.lo; q < r.hi; ++q) m += (int64_t)qp[q];
+        need = std::max(need, std::min(m, (r.hi - r.lo) * n_r));
+    }
+    if (need > (int64_t)0x7FFFFFFF - 64) return SW_ERANGE;
+    if (need > d.search_cap) {
+        for (int b = 0; b < 2; ++b) {
+            if ((rc = grow(&d.search_pairs[b], 2 * need)) || (rc = grow(&d.search_res[b], need)) ||
+                (rc = grow(&d.search_id[b], need)))
+                return d.search_cap = 0, rc;
+        }
+        d.search_cap = need;
+    }
+    int64_t candidates = 0;
+    for (size_t b = 0; b < ranges.size(); ++b) {
+        const int buf = (int)(b & 1);
+        int64_t n_b = 0;
+        {
+            std::lock_guard<std::mutex> lock(g_mutex);
+            // the block two back must have released this buffer set
+            if (b >= 2) HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[3 + buf], 0), "hipStreamWaitEvent");
+            HIP_TRY(hipMemsetAsync(x.counters + kKmOut, 0, sizeof(uint64_t), sd), "clear counter");
+            if ((rc = discover_join(x, prep, mode, min_shared, ranges[b], d.search_pairs[buf], nullptr, need, sd)))
+                return rc;
+            if ((rc = read_counters(x, sd))) return rc;  // synchronises the discovery stream only
+            n_b = (int64_t)x.host[kKmOut];
+            if (n_b > need) {
+                std::snprintf(g_last_error, sizeof(g_last_error), "sw_search: a block found more pairs than matches");
+                return SW_EDEVICE;
+            }
+            HIP_TRY(hipEventRecord(d.search_ev[1 + buf], sd), "hipEventRecord");
+            HIP_TRY(hipStreamWaitEvent(sa, d.search_ev[1 + buf], 0), "hipStreamWaitEvent");
+        }
+        candidates += n_b;
+        // the alignment and the filter of this block are enqueued on the
+        // alignment stream; the next block's discovery runs meanwhile
+        if (n_b > 0) {
+            if ((rc = align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r,
+                                 d.search_pairs[buf], n_b, scoring, d.search_res[buf], WsMode::library, nullptr, 0, sa,
+                                 SW_NO_GRAPH)))
+                return rc;
+            if ((rc = sw_identity(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r,
+                                  d.search_pairs[buf], n_b, scoring, d.search_res[buf], ani_permille, cov_permille,
+                                  d.search_id[buf], sa, 0)))
+                return rc;
+            HIP_TRY(launch_edges(d.search_pairs[buf], d.search_res[buf], d.search_id[buf], n_b, edges_dev,
+                                 edge_results_dev, edge_ident_dev, edge_cap, d.search_count, sa),
+                    "edges launch");
+        }
+        HIP_TRY(hipEventRecord(d.search_ev[3 + buf], sa), "hipEventRecord");
+    }
+    HIP_TRY(hipMemcpyAsync(d.search_count_host, d.search_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, sa),
+            "read counter");
+    HIP_TRY(hipStreamSynchronize(sa), "hipStreamSynchronize");
+    HIP_TRY(hipStreamSynchronize(sd), "hipStreamSynchronize");
+    stats->candidates = candidates;
+    stats->edges = (int64_t)*d.search_count_host;
+    stats->blocks = (int32_t)ranges.size();
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        if ((rc = read_and_clear_errors(d, sa))) return rc;
+    }
+    return stats->edges > edge_cap ? SW_ENOMEM : SW_OK;
 }
 
 int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_q, const void* r_packed_dev,
@@ -1109,6 +1409,7 @@ int sw_set_tuning(const sw_tuning* t)
     if (t->blocks_per_cu > 8 || t->blocks_per_cu < -1) return SW_EINVAL;
     for (int g : {t->group16_max_len, t->group8_max_len})
         if (g > 0 && (g < 64 || g > kMaxP16Len || (g & (g - 1)) != 0)) return SW_EINVAL;
+    if (!bucket_lanes_valid(t->bucket_lanes, 16)) return SW_EINVAL;  // the checks that hold for any R
     std::lock_guard<std::mutex> lock(g_mutex);
     Device* d = nullptr;
     int rc = get_device(&d);
@@ -1116,14 +1417,17 @@ int sw_set_tuning(const sw_tuning* t)
     const int R = t->rows_per_lane > 0 ? t->rows_per_lane : d->R;
     const int im = t->inter_max_len > 0 ? t->inter_max_len : d->inter_max;
     if ((im + R - 1) / R > kMaxInterStrips) return SW_EINVAL;
+    if (!bucket_lanes_valid(t->bucket_lanes, R)) return SW_EINVAL;
     const int g16 = t->group16_max_len > 0 ? t->group16_max_len : d->group16_max;
     const int g8 = t->group8_max_len > 0 ? t->group8_max_len : d->group8_max;
-    const bool reorder = R != d->R || im != d->inter_max || g16 != d->group16_max || g8 != d->group8_max;
+    const bool reorder = R != d->R || im != d->inter_max || g16 != d->group16_max || g8 != d->group8_max ||
+                         std::memcmp(t->bucket_lanes, d->bucket_lanes, sizeof(d->bucket_lanes)) != 0;
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     d->R = R;
     d->inter_max = im;
     d->group16_max = g16;
     d->group8_max = g8;
+    std::memcpy(d->bucket_lanes, t->bucket_lanes, sizeof(d->bucket_lanes));
     if (t->blocks_per_cu > 0) d->bpc_user = t->blocks_per_cu;
     else if (t->blocks_per_cu == -1) d->bpc_user = 0;  // occupancy-derived
     if (reorder) {
@@ -1146,6 +1450,7 @@ int sw_get_tuning(sw_tuning* t)
     t->blocks_per_cu = blocks_per_cu(*d);
     t->group16_max_len = d->group16_max;
     t->group8_max_len = d->group8_max;
+    std::memcpy(t->bucket_lanes, d->bucket_lanes, sizeof(d->bucket_lanes));
     return SW_OK;
 }
 
@@ -1158,87 +1463,166 @@ int sw_matrix(int32_t matrix_id, int8_t* scores, char* letters)
 
 int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_seqs, const int32_t* pairs_dev,
                 int64_t n_pairs, const sw_scoring* scoring, sw_result* out_dev, void* stream_, int32_t reps,
-                sw_tuning* chosen, float* best_ms)
+                const char* cache_path, sw_tuning* chosen, float* best_ms, int32_t* bucket_trials)
 {
-    if (!chosen || n_pairs <= 0) return SW_EINVAL;
+    if (!chosen || !scoring || n_pairs <= 0 || n_seqs < 0 || !packed_dev || !offsets_dev || !pairs_dev || !out_dev)
+        return SW_EINVAL;
+    if (n_pairs > (int64_t)0x7FFFFFFF - 64) return SW_ERANGE;
     hipStream_t stream = (hipStream_t)stream_;
     if (reps < 1) reps = 1;
     sw_tuning orig{};
     int rc = sw_get_tuning(&orig);
     if (rc) return rc;
+    std::string arch;
+    int n_cu = 0, bpc = 0;
     {
         std::lock_guard<std::mutex> lock(g_mutex);
         Device* d = nullptr;
         if ((rc = get_device(&d))) return rc;
         if (d->bpc_user == 0) orig.blocks_per_cu = -1;  // restore the occupancy-derived grid
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, d->id), "hipGetDeviceProperties");
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+        n_cu = d->n_cu;
+        bpc = blocks_per_cu(*d);
     }
-    struct Cand {
-        int R, im, g8, g16;
-    };
-    std::vector<Cand> cands;
-    for (int R : {16, 8})
-        for (int im : {512, 768, 1024})
-            for (int g8 : {1024, 2048})
-                for (int g16 : {2048, 4096})
-                    if ((im + R - 1) / R <= kMaxInterStrips) cands.push_back({R, im, g8, g16});
+    // the pairs of each length bucket (host copies of the pairs and offsets)
+    std::vector<int64_t> offs((size_t)n_seqs + 1);
+    std::vector<int32_t> prs((size_t)n_pairs * 2);
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    HIP_TRY(hipMemcpy(offs.data(), offsets_dev, sizeof(int64_t) * offs.size(), hipMemcpyDeviceToHost), "autotune read");
+    HIP_TRY(hipMemcpy(prs.data(), pairs_dev, sizeof(int32_t) * prs.size(), hipMemcpyDeviceToHost), "autotune read");
+    std::vector<std::vector<int32_t>> by_bucket(kNumLenBuckets);
+    for (int64_t k = 0; k < n_pairs; ++k) {
+        const int64_t qi = prs[2 * k], ri = prs[2 * k + 1];
+        if (qi < 0 || qi >= n_seqs || ri < 0 || ri >= n_seqs) continue;
+        const int64_t m = offs[qi + 1] - offs[qi], n = offs[ri + 1] - offs[ri];
+        if (m <= 0 || n <= 0 || m > SW_MAX_SEQ_LEN || n > SW_MAX_SEQ_LEN) continue;
+        auto& v = by_bucket[ceil_log2(std::max(m, n))];
+        v.push_back((int32_t)qi);
+        v.push_back((int32_t)ri);
+    }
+    size_t most = 1;
+    for (const auto& v : by_bucket) most = std::max(most, v.size() / 2);
+    std::vector<TuneEntry> cache;
+    if (cache_path) cache = read_tune_cache(cache_path);
+    const TuneEntry key0{arch, n_cu, bpc, 0, scoring->gap_open, scoring->gap_extend, 0, 0, 0.f};
+
+    int32_t* sub_pairs = nullptr;
+    sw_result* sub_out = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-    std::vector<sw_result> ref((size_t)n_pairs), cur((size_t)n_pairs);
+    auto cleanup = [&]() {
+        (void)hipFree(sub_pairs);
+        (void)hipFree(sub_out);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc((void**)&sub_pairs, sizeof(int32_t) * 2 * most) != hipSuccess ||
+        hipMalloc((void**)&sub_out, sizeof(sw_result) * most) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return dev_error(hipGetLastError(), "autotune buffers");
+    }
+    // one untimed call (also the byte-identity check against `ref`), then
+    // `reps` timed calls; milliseconds per call
+    std::vector<sw_result> cur;
+    auto trial = [&](const sw_tuning& t, const int32_t* p_dev, int64_t np, sw_result* o_dev,
+                     std::vector<sw_result>& ref, float* ms) -> int {
+        int r = sw_set_tuning(&t);
+        if (r) return r;
+        if ((r = sw_batch_align(packed_dev, offsets_dev, n_seqs, p_dev, np, scoring, o_dev, stream, 0))) return r;
+        cur.resize((size_t)np);
+        HIP_TRY(hipMemcpyAsync(cur.data(), o_dev, sizeof(sw_result) * (size_t)np, hipMemcpyDeviceToHost, stream),
+                "autotune readback");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (ref.empty()) ref = cur;
+        else if (std::memcmp(ref.data(), cur.data(), sizeof(sw_result) * (size_t)np) != 0) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "autotune: results differ between kernel shapes (rows_per_lane %d)", t.rows_per_lane);
+            return SW_EDEVICE;
+        }
+        HIP_TRY(hipEventRecord(e0, stream), "hipEventRecord");
+        for (int k = 0; k < reps; ++k)
+            if ((r = sw_batch_align(packed_dev, offsets_dev, n_seqs, p_dev, np, scoring, o_dev, stream, 0))) return r;
+        HIP_TRY(hipEventRecord(e1, stream), "hipEventRecord");
+        HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+        HIP_TRY(hipEventElapsedTime(ms, e0, e1), "hipEventElapsedTime");
+        *ms /= (float)reps;
+        return SW_OK;
+    };
+    int trials = 0;
     float best = 1e30f;
     sw_tuning best_t = orig;
-    bool have_ref = false;
-    for (const Cand& c : cands) {
-        sw_tuning t{c.R, c.im, -1, c.g16, c.g8};  // occupancy-derived grid
-        if ((rc = sw_set_tuning(&t))) break;
-        // warm-up run, also the tile-independence check
-        if ((rc = sw_batch_align(packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, scoring, out_dev, stream, 0)))
-            break;
-        if (hipMemcpyAsync(cur.data(), out_dev, sizeof(sw_result) * (size_t)n_pairs, hipMemcpyDeviceToHost, stream) !=
-                hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess) {
-            rc = dev_error(hipGetLastError(), "autotune readback");
-            break;
+    std::vector<sw_result> full_ref;
+    for (int R : {16, 8}) {
+        sw_tuning t = orig;
+        t.rows_per_lane = R;
+        t.inter_max_len = std::min(orig.inter_max_len, kMaxInterStrips * R);
+        t.blocks_per_cu = -1;
+        std::memset(t.bucket_lanes, 0, sizeof(t.bucket_lanes));
+        // buckets in increasing length: the start passes of a bucket's pairs
+        // fall in this or shorter buckets, already chosen
+        for (int b = 0; b < kNumLenBuckets && rc == SW_OK; ++b) {
+            const int64_t np = (int64_t)by_bucket[b].size() / 2;
+            if (np == 0) continue;
+            TuneEntry key = key0;
+            key.rows_per_lane = R;
+            key.bucket = b;
+            const TuneEntry* hit = find_tune_entry(cache, key);
+            if (hit && lanes_allowed(b, hit->lanes, R)) {
+                t.bucket_lanes[b] = (int8_t)hit->lanes;
+                continue;
+            }
+            if (hipMemcpy(sub_pairs, by_bucket[b].data(), sizeof(int32_t) * 2 * (size_t)np,
+                          hipMemcpyHostToDevice) != hipSuccess) {
+                rc = dev_error(hipGetLastError(), "autotune pairs");
+                break;
+            }
+            std::vector<sw_result> ref;
+            float bms = 1e30f;
+            int bl = 64;
+            for (int lanes : {1, 8, 16, 64}) {
+                if (!lanes_allowed(b, lanes, R)) continue;
+                sw_tuning c = t;
+                c.bucket_lanes[b] = (int8_t)lanes;
+                float ms = 0.f;
+                if ((rc = trial(c, sub_pairs, np, sub_out, ref, &ms))) break;
+                ++trials;
+                if (ms < bms) {
+                    bms = ms;
+                    bl = lanes;
+                }
+            }
+            if (rc) break;
+            t.bucket_lanes[b] = (int8_t)bl;
+            key.lanes = bl;
+            key.ms = bms;
+            put_tune_entry(cache, key);
         }
-        if (!have_ref) {
-            ref = cur;
-            have_ref = true;
-        } else if (std::memcmp(ref.data(), cur.data(), sizeof(sw_result) * (size_t)n_pairs) != 0) {
-            std::snprintf(g_last_error, sizeof(g_last_error),
-                          "autotune: results differ between kernel shapes (R=%d inter_max=%d group8_max=%d "
-                          "group16_max=%d)",
-                          c.R, c.im, c.g8, c.g16);
-            rc = SW_EDEVICE;
-            break;
-        }
-        (void)hipEventRecord(e0, stream);
-        for (int k = 0; k < reps && rc == SW_OK; ++k)
-            rc = sw_batch_align(packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, scoring, out_dev, stream, 0);
-        (void)hipEventRecord(e1, stream);
         if (rc) break;
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            rc = dev_error(hipGetLastError(), "autotune timing");
-            break;
-        }
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= (float)reps;
+        if ((rc = trial(t, pairs_dev, n_pairs, out_dev, full_ref, &ms))) break;
         if (ms < best) {
             best = ms;
             best_t = t;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    cleanup();
     if (rc) {
         (void)sw_set_tuning(&orig);
         return rc;
     }
-    rc = sw_set_tuning(&best_t);
-    if (rc) return rc;
-    rc = sw_get_tuning(chosen);
-    if (rc) return rc;
+    best_t.blocks_per_cu = orig.blocks_per_cu;
+    if ((rc = sw_set_tuning(&best_t))) return rc;
+    // out_dev: the whole workload under the chosen tuning
+    if ((rc = sw_batch_align(packed_dev, offsets_dev, n_seqs, pairs_dev, n_pairs, scoring, out_dev, stream, 0)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if ((rc = sw_get_tuning(chosen))) return rc;
     if (best_ms) *best_ms = best;
+    if (bucket_trials) *bucket_trials = trials;
+    if (cache_path && !write_tune_cache(cache_path, cache)) return SW_EINVAL;
     return SW_OK;
 }
 

@@ -405,6 +405,7 @@ __host__ __device__ constexpr int64_t boundary_buf_words(int P)
     return (P == 1 ? (int64_t)kMaxInterChunks : (int64_t)(kMaxP16Len / 8)) * (kWave / P) * 8;
 }
 
+
 // ONE: sweep only super-strip `one_ss` of each group (it may differ between
 // groups; -1 for none), reading its input row from boundary buffer `one_buf`
 // of the slot and writing nothing: the exact-cell pass after the packed
@@ -714,12 +715,35 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
 
+// Maximum of three packed cells.  With F16 the 16-bit values are read as
+// half-precision bit patterns and one v_pk_maximum3_f16 takes the IEEE
+// maximum: for patterns below 0x7C00 (non-negative, finite, subnormals kept
+// by the kernels' float mode) the order of the halves is the order of the
+// integers, and a maximum only selects one of its inputs, so the result is
+// the integer maximum, bit for bit.  Every value a pass holds stays at or
+// below its pair's best score, so F16 applies while that bound is below
+// kF16MaxScore.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+constexpr int kF16MaxScore = 31000;
+template <bool F16>
+__device__ __forceinline__ u16x2 max3_u16x2(u16x2 a, u16x2 b, u16x2 c)
+{
+    if constexpr (F16) {
+        const f16x2 m = __builtin_elementwise_maximum(
+            __builtin_elementwise_maximum(__builtin_bit_cast(f16x2, a), __builtin_bit_cast(f16x2, b)),
+            __builtin_bit_cast(f16x2, c));
+        return __builtin_bit_cast(u16x2, m);
+    } else {
+        return __builtin_elementwise_max(__builtin_elementwise_max(a, b), c);
+    }
+}
+
 // Keeps the compiler from moving memory accesses across this point (LDS
 // hand-over between lanes of one wave; the hardware keeps a wave's LDS
 // accesses in order).
 __device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
 
-template <int P, bool REV>
+template <int P, bool REV, bool F16>
 __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, uint32_t* xw, uint32_t* __restrict__ slot,
                                   int64_t Q0, int M, int64_t R0, int N, int target)
 {
@@ -807,9 +831,11 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         const uint4* in4 = read_top ? reinterpret_cast<const uint4*>(grp_slot + bi * BW) : g_zero_row;
         const int in_stride = read_top ? G * 2 : 0;
         uint4* out4 = reinterpret_cast<uint4*>(grp_slot + bo * BW);
-        uint32_t H[8], E[8], Mx[8];
+        uint32_t H[8], E[8], Mx[4];  // Mx[k]: running maximum of registers 2k and 2k + 1
 #pragma unroll
-        for (int i = 0; i < 8; ++i) H[i] = E[i] = Mx[i] = 0;
+        for (int i = 0; i < 8; ++i) H[i] = E[i] = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Mx[i] = 0;
         uint32_t up_prev = 0, fo_prev = 0, pw0 = 0, pw1 = 0;  // previous profile entry
         uint32_t botp[8];
 #pragma unroll
@@ -976,17 +1002,18 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 const uint32_t up_cur = __builtin_amdgcn_perm(H[7], top[k], 0x05040100u);
                 uint32_t Fv = __builtin_amdgcn_perm(fo_prev, top[k], 0x05040302u);
                 uint32_t hd = up_prev;
+                u16x2 h_even = {0, 0};
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const u16x2 d = __builtin_elementwise_sub_sat(as_u16x2(hd) + as_u16x2(sw[i]), bias2);
-                    const u16x2 h =
-                        __builtin_elementwise_max(__builtin_elementwise_max(d, as_u16x2(E[i])), as_u16x2(Fv));
+                    const u16x2 h = max3_u16x2<F16>(d, as_u16x2(E[i]), as_u16x2(Fv));
                     hd = H[i];
                     H[i] = as_u32(h);
                     const u16x2 hg = __builtin_elementwise_sub_sat(h, go2);
                     E[i] = as_u32(__builtin_elementwise_max(__builtin_elementwise_sub_sat(as_u16x2(E[i]), ge2), hg));
                     Fv = as_u32(__builtin_elementwise_max(__builtin_elementwise_sub_sat(as_u16x2(Fv), ge2), hg));
-                    Mx[i] = as_u32(__builtin_elementwise_max(as_u16x2(Mx[i]), h));
+                    if (i & 1) Mx[i / 2] = as_u32(max3_u16x2<F16>(as_u16x2(Mx[i / 2]), h_even, h));
+                    else h_even = h;
                 }
                 fo_prev = Fv;
                 up_prev = up_cur;
@@ -1044,7 +1071,7 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         block_fence();
         uint32_t m2 = Mx[0];
 #pragma unroll
-        for (int i = 1; i < 8; ++i) m2 = as_u32(__builtin_elementwise_max(as_u16x2(m2), as_u16x2(Mx[i])));
+        for (int i = 1; i < 4; ++i) m2 = as_u32(__builtin_elementwise_max(as_u16x2(m2), as_u16x2(Mx[i])));
         int smax = (int)max(m2 & 0xFFFFu, m2 >> 16);
 #pragma unroll
         for (int o = 1; o < P; o <<= 1) smax = max(smax, __shfl_xor(smax, o, kWave));
@@ -1179,7 +1206,10 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     if (packed) {
         uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
         if (a.phase != 2) {
-            const StripPick pf = packed_sweep<P, false>(a, prof, xw, slot, qoff, m, roff, n, 0);
+            // every value of the forward pass is at most 11 min(m, n)
+            const bool f16 = P == 1 || uni(wave_max(11 * min(m, n))) <= kF16MaxScore;
+            const StripPick pf = f16 ? packed_sweep<P, false, true>(a, prof, xw, slot, qoff, m, roff, n, 0)
+                                     : packed_sweep<P, false, false>(a, prof, xw, slot, qoff, m, roff, n, 0);
             f = group_sweep<R, P, false, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, pf.ss, pf.buf);
             forward_done(pf.s);
             if (a.phase == 1) return;
@@ -1187,7 +1217,10 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
         const bool hs = f.s > 0;
         const int64_t qr = qoff + (hs ? f.i : 0), rr = roff + (hs ? f.j : 0);
         const int mr = hs ? f.i + 1 : 0, nr = hs ? f.j + 1 : 0;
-        const StripPick pr = packed_sweep<P, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+        // and every value of the start pass at most the score
+        const bool f16 = P == 1 || uni(wave_max(f.s)) <= kF16MaxScore;
+        const StripPick pr = f16 ? packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s)
+                                 : packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
         const Best r = group_sweep<R, P, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s,
                                                            hs ? pr.ss : -1, pr.buf);
         if (pid >= 0 && u == 0) {
@@ -1347,12 +1380,11 @@ __device__ __forceinline__ int ceil_log2(int64_t x)
 // Lanes per pair of a work cell: 1 for the short-pair cells; for long pairs
 // by length bucket 8 up to group8_max, 16 up to group16_max (both at most
 // kMaxP16Len residues), 64 beyond.
-__device__ __forceinline__ int cell_kind(int cell, int group8_max, int group16_max)
+__device__ __forceinline__ int cell_kind(int cell, const Args& a)
 {
     if (cell < kInterCells) return 1;
     const int bucket = (cell - kInterCells) / kWideCostBins;
-    if ((1 << bucket) <= min(group8_max, kMaxP16Len)) return 8;
-    return (1 << bucket) <= min(group16_max, kMaxP16Len) ? 16 : 64;
+    return bucket_group_kind(bucket, a.bucket_kind[bucket], a.group8_max_len, a.group16_max_len);
 }
 
 // Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
@@ -1363,7 +1395,8 @@ __device__ __forceinline__ int cell_kind(int cell, int group8_max, int group16_m
 __device__ __forceinline__ int cell_of(const Args& a, int64_t m, int64_t n)
 {
     const int64_t mx = m > n ? m : n;
-    if (mx <= a.inter_max_len) {
+    const int ov = a.bucket_kind[ceil_log2(mx)];
+    if (ov == 1 || (ov == 0 && mx <= a.inter_max_len)) {
         const int s = (int)((m + a.rows_per_lane - 1) / a.rows_per_lane);
         const int c = (int)((n + 7) / 8);
         return (s - 1) * kMaxInterChunks + (c - 1);
@@ -1468,7 +1501,7 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
     for (int i = 0; i < per; ++i) {
         const int c = shard_sum(i);
         sum += c;
-        const int kind = cell_kind(cells[i], a.group8_max_len, a.group16_max_len);
+        const int kind = cell_kind(cells[i], a);
         if (kind == 64) c64 += c;
         else if (kind == 16) c16 += c;
         else if (kind == 8) c8 += c;

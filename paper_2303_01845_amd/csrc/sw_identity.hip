@@ -30,6 +30,8 @@
 // an optimal alignment that starts at the reported start scores above zero
 // (otherwise a later start would be optimal too, and the reported start is
 // the latest one), so no dropped cell lies on an alignment that can win.
+#include <algorithm>
+
 #include "identity_internal.h"
 
 namespace swk {
@@ -289,6 +291,49 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
 hipError_t launch_identity(const IdentArgs& a, int blocks, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_identity, dim3((unsigned)blocks), dim3(64 * kIdentWavesPerBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+// The edges of the similarity graph: pairs whose identity record keeps them,
+// with their alignment and identity records, appended to the output at
+// *count in no particular order (one atomic per wave; slots past `cap` are
+// counted, not written).
+__global__ void k_edges(const int32_t* __restrict__ pairs, const sw_result* __restrict__ res,
+                        const sw_identity_result* __restrict__ id, int64_t n, int32_t* __restrict__ e_pairs,
+                        sw_result* __restrict__ e_res, sw_identity_result* __restrict__ e_id, int64_t cap,
+                        unsigned long long* count)
+{
+    const int lane = threadIdx.x & 63;
+    // every lane of a wave takes the same trips (the ballot needs all of them)
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = base + threadIdx.x;
+        const bool keep = k < n && id[k].keep == 1;
+        const unsigned long long mask = __ballot(keep);
+        if (mask == 0) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned long long first = 0;
+        if (lane == leader) first = atomicAdd(count, (unsigned long long)__popcll(mask));
+        first = __shfl(first, leader, 64);
+        if (keep) {
+            const int64_t slot = (int64_t)(first + (unsigned long long)__popcll(mask & ((1ull << lane) - 1)));
+            if (slot < cap) {
+                e_pairs[2 * slot] = pairs[2 * k];
+                e_pairs[2 * slot + 1] = pairs[2 * k + 1];
+                e_res[slot] = res[k];
+                e_id[slot] = id[k];
+            }
+        }
+    }
+}
+
+hipError_t launch_edges(const int32_t* pairs, const sw_result* res, const sw_identity_result* id, int64_t n,
+                        int32_t* e_pairs, sw_result* e_res, sw_identity_result* e_id, int64_t cap,
+                        unsigned long long* count, hipStream_t stream)
+{
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_edges, dim3((unsigned)blocks), dim3(256), 0, stream, pairs, res, id, n, e_pairs, e_res,
+                           e_id, cap, count);
     return hipGetLastError();
 }
 

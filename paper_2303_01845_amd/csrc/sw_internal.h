@@ -100,7 +100,23 @@ struct Args {
     int32_t group8_max_len;    // longest pair of an 8-lane group (power of two, <= group16_max_len)
     int32_t phase;             // 0: both passes per item; 1: forward pass only (writes score
                                // and end); 2: start pass only (reads them from out)
+    int8_t bucket_kind[kNumLenBuckets];  // lanes per pair of each length bucket, 0: the rule
 };
+static_assert(kNumLenBuckets == SW_NUM_BUCKETS, "one override per length bucket");
+
+// Lanes per pair of the pairs of a length bucket that do not get one lane
+// each: the bucket's override if it names a group, else the threshold rule
+// (8-lane groups up to group8_max, 16-lane up to group16_max, both capped at
+// kMaxP16Len, a whole wave beyond).  Shared by the host's ordering and the
+// device's cell bookkeeping so that both agree on every cell.
+__host__ __device__ inline int bucket_group_kind(int bucket, int override_kind, int group8_max, int group16_max)
+{
+    if (override_kind > 1) return override_kind;
+    const int len = 1 << bucket;
+    const int g8 = group8_max < kMaxP16Len ? group8_max : kMaxP16Len;
+    const int g16 = group16_max < kMaxP16Len ? group16_max : kMaxP16Len;
+    return len <= g8 ? 8 : len <= g16 ? 16 : 64;
+}
 
 // launchers (sw_device.hip); all asynchronous on `stream`
 hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err, hipStream_t stream);

@@ -94,6 +94,11 @@ def test_tuning_argument_checks():
                 (0, 0, 0, 3000), (0, 0, 0, 8192), (0, 0, 0, 32), (0, 0, -2, 0), (0, 0, 0, 0, 32),
                 (0, 0, 0, 0, 3000), (0, 0, 0, 0, 8192)]:
         assert L.sw_set_tuning(ctypes.byref(sw.Tuning(*bad))) == sw.SW_EINVAL
+    for b, lanes in [(0, 2), (5, 32), (11, 1), (13, 8), (13, 16), (16, -1), (3, 4)]:
+        table = [0] * sw.NUM_BUCKETS
+        table[b] = lanes
+        t = sw.Tuning(0, 0, 0, 0, 0, (ctypes.c_int8 * sw.NUM_BUCKETS)(*table))
+        assert L.sw_set_tuning(ctypes.byref(t)) == sw.SW_EINVAL, (b, lanes)
     assert L.sw_get_tuning(None) == sw.SW_EINVAL
     assert L.sw_matrix(1, None, None) == sw.SW_EINVAL
 
