@@ -405,6 +405,13 @@ __host__ __device__ constexpr int64_t boundary_buf_words(int P)
     return (P == 1 ? (int64_t)kMaxInterChunks : (int64_t)(kMaxP16Len / 8)) * (kWave / P) * 8;
 }
 
+// The same for N columns: a whole wave also runs the start passes of longer
+// pairs in narrow cells (one group, one word per column, rounded to 256
+// bytes); three such buffers of 65,536 columns fill the least slot.
+__host__ __device__ constexpr int64_t narrow_buf_words(int P, int N)
+{
+    return P == 64 && N > kMaxP16Len ? ((((int64_t)N + 7) / 8) * 8 + 63) & ~(int64_t)63 : boundary_buf_words(P);
+}
 
 // ONE: sweep only super-strip `one_ss` of each group (it may differ between
 // groups; -1 for none), reading its input row from boundary buffer `one_buf`
@@ -441,7 +448,7 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
                             StripPick* pick_out = nullptr)
 {
     static_assert(!SCAN || (WIDE && !ONE), "the scan is the whole-wave path's score pass");
-    const int64_t BUFW = WIDE ? wide_buf_words(N) : boundary_buf_words(P);
+    const int64_t BUFW = WIDE ? wide_buf_words(N) : narrow_buf_words(P, N);
     constexpr int TB = WIDE ? 12 : 16;  // tag bits of the per-row trackers
     constexpr int SW = WIDE ? 4 : 2;    // uint4 per boundary chunk of 8 columns
     constexpr int G = kWave / P;        // groups per wave
@@ -725,6 +732,13 @@ __device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(
 // kF16MaxScore.
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 constexpr int kF16MaxScore = 31000;
+// Largest score a packed pass may hold: every cell stays at or below the
+// pair's score and the biased diagonal sum at most 15 above it, all below
+// 2^16.
+constexpr int kPackedMaxScore = 65504;
+// Widest region the narrow recompute tracks: its 16-bit column tags count
+// steps of the wavefront (columns plus 8 per lane of offset).
+constexpr int kNarrowMaxCols = 65000;
 template <bool F16>
 __device__ __forceinline__ u16x2 max3_u16x2(u16x2 a, u16x2 b, u16x2 c)
 {
@@ -748,7 +762,7 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                                   int64_t Q0, int M, int64_t R0, int N, int target)
 {
     constexpr int G = kWave / P;
-    constexpr int64_t BW = boundary_buf_words(P);
+    const int64_t BW = narrow_buf_words(P, N);
     const int lane = threadIdx.x & (kWave - 1);
     const int u = lane % P, g = lane / P;
     const uint8_t* prof_lane = prof + lane * prof_bytes(16);
@@ -1245,10 +1259,26 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
             const bool hs = f.s > 0;
             const int64_t qr = qoff + (hs ? f.i : 0), rr = roff + (hs ? f.j : 0);
             const int mr = hs ? f.i + 1 : 0, nr = hs ? f.j + 1 : 0;
-            StripPick pr{0, -1, 0};
-            group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr);
-            const Best r = group_sweep<R, P, true, true, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s,
-                                                               hs ? pr.ss : -1, pr.buf);
+            Best r{0, -1, -1};
+            // Every value of the start pass is at most the score, so when the
+            // score (plus the 15 of a biased substitution score) fits 16 bits
+            // the pass runs in packed cells, and its recompute in narrow
+            // cells whose 16-bit column tags cover the region's columns.
+            bool packed_start = false;
+            if constexpr (R == 16) packed_start = uni(f.s) <= kPackedMaxScore && uni(nr) <= kNarrowMaxCols;
+            if (packed_start) {
+                uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
+                const StripPick pr = uni(f.s) <= kF16MaxScore
+                                         ? packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s)
+                                         : packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+                r = group_sweep<R, P, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                         pr.buf);
+            } else {
+                StripPick pr{0, -1, 0};
+                group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr);
+                r = group_sweep<R, P, true, true, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                        pr.buf);
+            }
             if (pid >= 0 && u == 0) {
                 if (hs && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
                 write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
