@@ -199,10 +199,166 @@ __device__ __forceinline__ int64_t sweep_box(const int8_t* sub, int64_t* Hrow, i
     return fin;
 }
 
+// ---------------------------------------------------------------- 32-bit keys
+// Boxes of at most 511 x 511 residues (with gap penalties small enough, see
+// box32_ok) run the same wavefront with one 32-bit key per state:
+//   key = score << 18 | matches << 9 | pairs
+// where pairs counts aligned pairs.  A global alignment of an M x N box has
+// M + N - pairs columns, so most pairs is fewest columns and integer order of
+// keys is again the wanted lexicographic order (score, matches, -columns);
+// matches and pairs stay below 2^9, so the fields never borrow and keys add
+// along a path, for scores of either sign.  No cell is dropped: the row above
+// the box and the column left of it hold the exact keys of leading gaps
+// (score -(go + k ge)), so every value is the key of a real path from the
+// box's origin, and the states that cannot exist there (E left of the box, F
+// above it) are a constant that loses every maximum.  Every value then lies
+// within the bounds box32_ok checks.  A diagonal step adds one entry of a
+// 24 x 24 table in LDS (score, match and pair together).
+constexpr int kKey32ScoreShift = 18;
+constexpr int kKey32MatchShift = 9;
+constexpr int kKey32Field = 511;
+constexpr int32_t kNegKey32 = -(1 << 30);
+
+__device__ __forceinline__ int32_t gap_key32(int64_t go, int64_t ge, int64_t k)
+{
+    return -(int32_t)((go + k * ge) << kKey32ScoreShift);  // a leading gap of k + 1 residues
+}
+
+__host__ __device__ inline bool box32_ok(int M, int N, int go, int ge)
+{
+    if (M > kKey32Field || N > kKey32Field || go > 4096 || ge > 4096) return false;
+    const int64_t mn = M < N ? M : N;
+    // the most negative value a cell can hold (maxima, so at least the score
+    // of one simple path to it) and the largest positive one, both inside
+    // the 14-bit signed score field with room for one more gap step
+    const int64_t low = 4 * mn + 2 * (int64_t)go + (int64_t)ge * (M + N) + go + ge;
+    return low <= 8000 && 11 * mn <= 8000;
+}
+
+template <int R>
+__device__ __forceinline__ int32_t sweep_box32(const int32_t* step_tab, int32_t* Hrow, int32_t* Frow,
+                                               const uint32_t* qnib, const uint32_t* qhib, const uint32_t* rnib,
+                                               const uint32_t* rhib, int32_t go, int32_t ge, int M, int N,
+                                               int64_t Q0, int64_t R0, int lane, bool& bad_code)
+{
+    constexpr int kStrip = 64 * R;
+    const int32_t GO = -(go << kKey32ScoreShift), GE = -(ge << kKey32ScoreShift);
+    const int n_strips = (M + kStrip - 1) / kStrip;
+    int32_t fin = kNegKey32;
+    for (int st = 0; st < n_strips; ++st) {
+        const int base = st * kStrip;
+        const int rows = min(kStrip, M - base);
+        const int i0 = base + R * lane;
+        const bool ok0 = R * lane < rows;
+        const int32_t* tabr[R];
+        uint32_t qcr[R];
+        int32_t E[R], Hleft[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uint32_t qc = R * lane + r < rows ? code_at(qnib, qhib, Q0 + i0 + r) : 0u;
+            if (qc >= (uint32_t)kNumSym) {
+                bad_code = true;
+                qc = 0;
+            }
+            qcr[r] = qc;
+            tabr[r] = step_tab + qc * kNumSym;
+            E[r] = kNegKey32;                         // E left of the box cannot exist
+            Hleft[r] = gap_key32(go, ge, i0 + r);     // H left of the box: a leading gap of i + 1
+        }
+        // lane 0's first diagonal: the origin (strip 0) or the column left of the box
+        int32_t diag_next = (lane == 0) ? (st == 0 ? 0 : gap_key32(go, ge, base - 1)) : kNegKey32;
+        int32_t outH = kNegKey32, outF = kNegKey32;
+        uint32_t rc_prev = 0;
+        uint32_t cur = code_at(rnib, rhib, R0 + lane);
+        uint32_t nxt = code_at(rnib, rhib, R0 + 64 + lane);
+        const bool above = st > 0;
+        int32_t curH = 0, curF = 0, nxtH = 0, nxtF = 0;
+        if (above) {
+            curH = Hrow[lane];
+            curF = Frow[lane];
+            nxtH = Hrow[min(64 + lane, kIdentMaxCols - 1)];
+            nxtF = Frow[min(64 + lane, kIdentMaxCols - 1)];
+        }
+        const int lanes_used = (rows + R - 1) / R;
+        const int steps = N + lanes_used - 1;
+        for (int t = 0; t < steps; ++t) {
+            if (t > 0 && (t & 63) == 0) {
+                cur = nxt;
+                nxt = code_at(rnib, rhib, R0 + t + 64 + lane);
+                if (above) {
+                    curH = nxtH;
+                    curF = nxtF;
+                    const int c = min(t + 64 + lane, kIdentMaxCols - 1);
+                    nxtH = Hrow[c];
+                    nxtF = Frow[c];
+                }
+            }
+            const int src = t & 63;
+            const uint32_t rc_new = readlane32(cur, src);
+            const uint32_t rc_up = (uint32_t)__shfl_up((int)rc_prev, 1, 64);
+            const uint32_t rc = lane == 0 ? rc_new : rc_up;
+            rc_prev = rc;
+            int32_t upH = __shfl_up(outH, 1, 64);
+            int32_t upF = __shfl_up(outF, 1, 64);
+            const int32_t topH = (int32_t)readlane32((uint32_t)curH, src);
+            const int32_t topF = (int32_t)readlane32((uint32_t)curF, src);
+            if (lane == 0) {
+                // the row above: the previous strip's bottom row, or above
+                // the box the keys of a leading gap (no F there)
+                upH = above ? topH : gap_key32(go, ge, t);
+                upF = above ? topF : kNegKey32;
+            }
+            const int32_t diag = diag_next;
+            diag_next = upH;
+            const int j = t - lane;
+            if (ok0 && j >= 0 && j < N) {
+                uint32_t rcc = rc;
+                if (rcc >= (uint32_t)kNumSym) {
+                    bad_code = true;
+                    rcc = 0;
+                }
+                int32_t dg = diag;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int32_t d = dg + tabr[r][rcc];
+                    E[r] = max(E[r] + GE, Hleft[r] + GO);
+                    const int32_t F = max(upF + GE, upH + GO);
+                    const int32_t H = max(d, max(E[r], F));
+                    dg = Hleft[r];
+                    Hleft[r] = H;
+                    upH = H;
+                    upF = F;
+                    if (j == N - 1 && i0 + r == M - 1) fin = H;
+                }
+                outH = upH;
+                outF = upF;
+                if (lane == 63 && st + 1 < n_strips) {
+                    Hrow[j] = upH;
+                    Frow[j] = upF;
+                }
+            } else if (j == -1) {
+                // the column left of the box, for the next lane's diagonal
+                outH = gap_key32(go, ge, i0 + R - 1);
+                outF = kNegKey32;
+            } else {
+                outH = kNegKey32;
+                outF = kNegKey32;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the bottom row is in memory
+    }
+    return fin;
+}
+
 __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentArgs a)
 {
     __shared__ int8_t sub[kNumSym * kNumSym];
-    for (int i = threadIdx.x; i < kNumSym * kNumSym; i += blockDim.x) sub[i] = a.subst[i];
+    __shared__ int32_t step32[kNumSym * kNumSym];  // diagonal step of a 32-bit key
+    for (int i = threadIdx.x; i < kNumSym * kNumSym; i += blockDim.x) {
+        sub[i] = a.subst[i];
+        const int match = (i / kNumSym) == (i % kNumSym) ? 1 : 0;
+        step32[i] = ((int32_t)a.subst[i] << kKey32ScoreShift) + (match << kKey32MatchShift) + 1;
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -261,6 +417,36 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
         const int64_t Q0 = qb + res.q_start, R0 = rb + res.r_start;
         int64_t fin;
         int fin_lane;
+        if (box32_ok(M, N, a.go, a.ge)) {
+            int32_t* H32 = reinterpret_cast<int32_t*>(Hrow);
+            int32_t* F32 = reinterpret_cast<int32_t*>(Frow);
+            int32_t f32;
+            if (M <= 64) {
+                f32 = sweep_box32<1>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
+                                     bad_code);
+                fin_lane = M - 1;
+            } else if (M <= 128) {
+                f32 = sweep_box32<2>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
+                                     bad_code);
+                fin_lane = (M - 1) / 2;
+            } else {
+                f32 = sweep_box32<4>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
+                                     bad_code);
+                fin_lane = ((M - 1) % 256) / 4;
+            }
+            if (lane == fin_lane) {
+                rec.score = f32 >> kKey32ScoreShift;  // arithmetic: a negative score stays negative
+                rec.matches = (f32 >> kKey32MatchShift) & kKey32Field;
+                rec.columns = M + N - (f32 & kKey32Field);
+                if (rec.score > 0)
+                    rec.keep = (1000 * (int64_t)rec.matches >= (int64_t)a.ani_permille * rec.columns) && covered;
+                else
+                    rec = sw_identity_result{0, 0, 0, 0};
+                if (rec.score != res.score) bad_box = true;
+                a.out[k] = rec;
+            }
+            continue;
+        }
         if (M <= 64) {
             fin = sweep_box<1>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
             fin_lane = M - 1;
