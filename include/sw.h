@@ -439,11 +439,12 @@ SW_API int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, i
  * to the outputs: edges_dev int32[2 * edge_cap] (query, reference),
  * edge_results_dev sw_result[edge_cap], edge_ident_dev
  * sw_identity_result[edge_cap], in no particular order (the set is exact).
- * Discovery runs on one internal stream and the alignment and the filter on
- * another, so the discovery of block b+1 overlaps the alignment of block b;
- * two sets of block buffers, kept by the library and grown to the largest
- * block, bound the memory.  Both streams start after the work already
- * enqueued on `stream`; the call returns when everything is done.
+ * Discovery, alignment and the filter run on three internal streams, so the
+ * discovery of block b+1 overlaps the alignment of block b and the
+ * alignment of block b+1 the filter of block b; two sets of block buffers,
+ * kept by the library and grown to the largest block, bound the memory.  The
+ * streams start after the work already enqueued on `stream`; the call
+ * returns when everything is done.
  * *stats receives the candidates, the edges (all of them, also when more
  * than edge_cap: then only edge_cap are written and the call returns
  * SW_ENOMEM) and the number of blocks.  Calls on one device run one at a

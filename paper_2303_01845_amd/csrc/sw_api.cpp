@@ -212,6 +212,9 @@ struct Workspace {
     int64_t* ident_scratch = nullptr;  // identity pass: two rows of columns per resident wave
     int64_t ident_scratch_words = 0;
     int32_t* ident_next = nullptr;     // its work counter
+    int32_t* ident_tiers = nullptr;    // its work order: tier counts and cursors
+    int32_t* ident_order = nullptr;    // and the pair indices in that order
+    int64_t ident_order_cap = 0;
     int8_t* ident_subst = nullptr;     // the matrix in packed-code order
 
     void drop_graphs()
@@ -236,6 +239,8 @@ struct Workspace {
         (void)hipFree(scratch);
         (void)hipFree(ident_scratch);
         (void)hipFree(ident_next);
+        (void)hipFree(ident_tiers);
+        (void)hipFree(ident_order);
         (void)hipFree(ident_subst);
         if (host_rank_start) (void)hipHostFree(host_rank_start);
     }
@@ -257,10 +262,10 @@ struct Device {
     int32_t* err = nullptr;
     void* static_ws = nullptr;                // kStaticWsBytes (sw_align_sets_static)
     hipStream_t capture_stream = nullptr;     // created by the first graph capture
-    // sw_search: its discovery and alignment streams, events and the two
-    // sets of per-block buffers (kept, grown to the largest block)
-    hipStream_t search_stream[2] = {nullptr, nullptr};
-    hipEvent_t search_ev[5] = {};  // start, discovery done x2, alignment done x2
+    // sw_search: its discovery, alignment and filter streams, events and the
+    // two sets of per-block buffers (kept, grown to the largest block)
+    hipStream_t search_stream[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t search_ev[7] = {};  // start, then per buffer set: discovered, aligned, filtered
     int64_t search_cap = 0;
     int32_t* search_pairs[2] = {nullptr, nullptr};
     sw_result* search_res[2] = {nullptr, nullptr};
@@ -1172,7 +1177,7 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
     DiscoverSpace* xp = nullptr;
     DiscoverPrep prep;
     std::vector<uint64_t> qp;
-    hipStream_t sd = nullptr, sa = nullptr;
+    hipStream_t sd = nullptr, sa = nullptr, si = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_mutex);
         if ((rc = get_device(&dp))) return rc;
@@ -1187,11 +1192,13 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
         }
         sd = d.search_stream[0];
         sa = d.search_stream[1];
-        // both streams start after the caller's earlier work
+        si = d.search_stream[2];
+        // the three streams start after the caller's earlier work
         HIP_TRY(hipEventRecord(d.search_ev[0], caller), "hipEventRecord");
         HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[0], 0), "hipStreamWaitEvent");
         HIP_TRY(hipStreamWaitEvent(sa, d.search_ev[0], 0), "hipStreamWaitEvent");
-        HIP_TRY(hipMemsetAsync(d.search_count, 0, sizeof(unsigned long long), sa), "clear counter");
+        HIP_TRY(hipStreamWaitEvent(si, d.search_ev[0], 0), "hipStreamWaitEvent");
+        HIP_TRY(hipMemsetAsync(d.search_count, 0, sizeof(unsigned long long), si), "clear counter");
         if ((rc = discover_prepare(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, k, sd, &xp,
                                    &prep)))
             return rc;
@@ -1225,7 +1232,7 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
         {
             std::lock_guard<std::mutex> lock(g_mutex);
             // the block two back must have released this buffer set
-            if (b >= 2) HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[3 + buf], 0), "hipStreamWaitEvent");
+            if (b >= 2) HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[5 + buf], 0), "hipStreamWaitEvent");
             HIP_TRY(hipMemsetAsync(x.counters + kKmOut, 0, sizeof(uint64_t), sd), "clear counter");
             if ((rc = discover_join(x, prep, mode, min_shared, ranges[b], d.search_pairs[buf], nullptr, need, sd)))
                 return rc;
@@ -1239,25 +1246,32 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
             HIP_TRY(hipStreamWaitEvent(sa, d.search_ev[1 + buf], 0), "hipStreamWaitEvent");
         }
         candidates += n_b;
-        // the alignment and the filter of this block are enqueued on the
-        // alignment stream; the next block's discovery runs meanwhile
+        // the block's alignment on the alignment stream, then its filter and
+        // edge compaction on the filter stream: the next block's discovery
+        // and alignment are enqueued meanwhile, so they can take the compute
+        // units the filter's last long boxes leave free
         if (n_b > 0) {
             if ((rc = align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r,
                                  d.search_pairs[buf], n_b, scoring, d.search_res[buf], WsMode::library, nullptr, 0, sa,
                                  SW_NO_GRAPH)))
                 return rc;
-            if ((rc = sw_identity(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r,
-                                  d.search_pairs[buf], n_b, scoring, d.search_res[buf], ani_permille, cov_permille,
-                                  d.search_id[buf], sa, 0)))
-                return rc;
-            HIP_TRY(launch_edges(d.search_pairs[buf], d.search_res[buf], d.search_id[buf], n_b, edges_dev,
-                                 edge_results_dev, edge_ident_dev, edge_cap, d.search_count, sa),
-                    "edges launch");
         }
         HIP_TRY(hipEventRecord(d.search_ev[3 + buf], sa), "hipEventRecord");
+        HIP_TRY(hipStreamWaitEvent(si, d.search_ev[3 + buf], 0), "hipStreamWaitEvent");
+        if (n_b > 0) {
+            if ((rc = sw_identity(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r,
+                                  d.search_pairs[buf], n_b, scoring, d.search_res[buf], ani_permille, cov_permille,
+                                  d.search_id[buf], si, 0)))
+                return rc;
+            HIP_TRY(launch_edges(d.search_pairs[buf], d.search_res[buf], d.search_id[buf], n_b, edges_dev,
+                                 edge_results_dev, edge_ident_dev, edge_cap, d.search_count, si),
+                    "edges launch");
+        }
+        HIP_TRY(hipEventRecord(d.search_ev[5 + buf], si), "hipEventRecord");
     }
-    HIP_TRY(hipMemcpyAsync(d.search_count_host, d.search_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, sa),
+    HIP_TRY(hipMemcpyAsync(d.search_count_host, d.search_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, si),
             "read counter");
+    HIP_TRY(hipStreamSynchronize(si), "hipStreamSynchronize");
     HIP_TRY(hipStreamSynchronize(sa), "hipStreamSynchronize");
     HIP_TRY(hipStreamSynchronize(sd), "hipStreamSynchronize");
     stats->candidates = candidates;
@@ -1265,7 +1279,7 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
     stats->blocks = (int32_t)ranges.size();
     {
         std::lock_guard<std::mutex> lock(g_mutex);
-        if ((rc = read_and_clear_errors(d, sa))) return rc;
+        if ((rc = read_and_clear_errors(d, si))) return rc;
     }
     return stats->edges > edge_cap ? SW_ENOMEM : SW_OK;
 }
@@ -1312,8 +1326,14 @@ int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
         }
         for (int a = 0; a < kNumSym; ++a)
             for (int b = 0; b < kNumSym; ++b) coded[a * kNumSym + b] = ncbi[idx[a] * kNumSym + idx[b]];
-        if ((rc = grow(&w.ident_subst, kNumSym * kNumSym)) || (rc = grow(&w.ident_next, 1))) return rc;
+        if ((rc = grow(&w.ident_subst, kNumSym * kNumSym)) || (rc = grow(&w.ident_next, 1)) ||
+            (rc = grow(&w.ident_tiers, 2 * kIdentTiers)))
+            return rc;
         HIP_TRY(hipMemcpy(w.ident_subst, coded, sizeof(coded), hipMemcpyHostToDevice), "upload matrix");
+    }
+    if (n_pairs > w.ident_order_cap) {
+        if ((rc = grow(&w.ident_order, n_pairs))) return w.ident_order_cap = 0, rc;
+        w.ident_order_cap = n_pairs;
     }
     const int blocks = d.n_cu * 4;  // four blocks of four waves per CU: four waves per SIMD
     const int64_t need = (int64_t)blocks * kIdentWavesPerBlock * 2 * kIdentMaxCols;
@@ -1344,7 +1364,9 @@ int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t 
     a.ani_permille = ani_permille;
     a.cov_permille = cov_permille;
     a.coverage_first = (flags & SW_COVERAGE_FIRST) ? 1 : 0;
-    HIP_TRY(hipMemsetAsync(w.ident_next, 0, sizeof(int32_t), stream), "clear counter");
+    a.order = w.ident_order;
+    // largest boxes first (the order kernels also clear the work counter)
+    HIP_TRY(launch_identity_order(a, w.ident_tiers, w.ident_order, stream), "identity order launch");
     HIP_TRY(launch_identity(a, blocks, stream), "identity launch");
     if (flags & SW_VALIDATE) return read_and_clear_errors(d, stream);
     return SW_OK;

@@ -31,6 +31,7 @@
 // (otherwise a later start would be optimal too, and the reported start is
 // the latest one), so no dropped cell lies on an alignment that can win.
 #include <algorithm>
+#include <type_traits>
 
 #include "identity_internal.h"
 
@@ -219,10 +220,37 @@ constexpr int kKey32MatchShift = 9;
 constexpr int kKey32Field = 511;
 constexpr int32_t kNegKey32 = -(1 << 30);
 
-__device__ __forceinline__ int32_t gap_key32(int64_t go, int64_t ge, int64_t k)
-{
-    return -(int32_t)((go + k * ge) << kKey32ScoreShift);  // a leading gap of k + 1 residues
-}
+// The two exact key formats: 32-bit (score, matches, pairs) for small boxes,
+// and the 64-bit (score, matches, 2^20 - 1 - columns) of the dropping sweep
+// above, here with exact borders and nothing dropped, for the boxes whose
+// values fit its score field (box64x_ok).
+struct Key32 {
+    typedef int32_t T;
+    static constexpr T kNeg = kNegKey32;
+    // a leading gap of k + 1 residues: its score, no pairs
+    static __device__ __forceinline__ T gap(int64_t go, int64_t ge, int64_t k)
+    {
+        return -(T)((go + k * ge) << kKey32ScoreShift);
+    }
+    static __device__ __forceinline__ T step(int64_t g) { return -(T)(g << kKey32ScoreShift); }
+    static __device__ __forceinline__ T up(T v) { return __shfl_up(v, 1, 64); }
+    static __device__ __forceinline__ T mx(T a, T b) { return a > b ? a : b; }
+    static __device__ __forceinline__ T lane_value(T v, int src) { return (T)readlane32((uint32_t)v, src); }
+};
+
+struct Key64 {
+    typedef int64_t T;
+    static constexpr T kNeg = kNegKey;
+    // a leading gap of k + 1 residues: its score and k + 1 columns
+    static __device__ __forceinline__ T gap(int64_t go, int64_t ge, int64_t k)
+    {
+        return kOriginKey - ((go + k * ge) << kScoreShift) - (k + 1);
+    }
+    static __device__ __forceinline__ T step(int64_t g) { return -((g << kScoreShift) + 1); }
+    static __device__ __forceinline__ T up(T v) { return shfl_up64(v); }
+    static __device__ __forceinline__ T mx(T a, T b) { return kmax(a, b); }
+    static __device__ __forceinline__ T lane_value(T v, int src) { return readlane64(v, src); }
+};
 
 __host__ __device__ inline bool box32_ok(int M, int N, int go, int ge)
 {
@@ -235,24 +263,38 @@ __host__ __device__ inline bool box32_ok(int M, int N, int go, int ge)
     return low <= 8000 && 11 * mn <= 8000;
 }
 
-template <int R>
-__device__ __forceinline__ int32_t sweep_box32(const int32_t* step_tab, int32_t* Hrow, int32_t* Frow,
-                                               const uint32_t* qnib, const uint32_t* qhib, const uint32_t* rnib,
-                                               const uint32_t* rhib, int32_t go, int32_t ge, int M, int N,
-                                               int64_t Q0, int64_t R0, int lane, bool& bad_code)
+__host__ __device__ inline bool box64x_ok(int M, int N, int go, int ge)
 {
+    const int64_t mn = M < N ? M : N;
+    const int64_t low = 4 * mn + 2 * (int64_t)go + (int64_t)ge * (M + N) + go + ge;
+    return low <= 4000000 && 11 * mn <= 4000000;  // the score field holds +-2^23
+}
+
+// The exact sweep: the wavefront of sweep_box with keys of format K, the
+// diagonal step of each (query, reference) code pair from a table in LDS,
+// exact keys of leading gaps above and left of the box (every value is the
+// key of a real path from the box's origin, so none is dropped) and a
+// constant that loses every maximum for the states that cannot exist there
+// (E left of the box, F above it).
+template <int R, typename K>
+__device__ __forceinline__ typename K::T sweep_box_exact(const typename K::T* step_tab, typename K::T* Hrow,
+                                                         typename K::T* Frow, const uint32_t* qnib,
+                                                         const uint32_t* qhib, const uint32_t* rnib,
+                                                         const uint32_t* rhib, int32_t go, int32_t ge, int M, int N,
+                                                         int64_t Q0, int64_t R0, int lane, bool& bad_code)
+{
+    typedef typename K::T T;
     constexpr int kStrip = 64 * R;
-    const int32_t GO = -(go << kKey32ScoreShift), GE = -(ge << kKey32ScoreShift);
+    const T GO = K::step(go), GE = K::step(ge);
     const int n_strips = (M + kStrip - 1) / kStrip;
-    int32_t fin = kNegKey32;
+    T fin = K::kNeg;
     for (int st = 0; st < n_strips; ++st) {
         const int base = st * kStrip;
         const int rows = min(kStrip, M - base);
         const int i0 = base + R * lane;
         const bool ok0 = R * lane < rows;
-        const int32_t* tabr[R];
-        uint32_t qcr[R];
-        int32_t E[R], Hleft[R];
+        const T* tabr[R];
+        T E[R], Hleft[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             uint32_t qc = R * lane + r < rows ? code_at(qnib, qhib, Q0 + i0 + r) : 0u;
@@ -260,19 +302,19 @@ __device__ __forceinline__ int32_t sweep_box32(const int32_t* step_tab, int32_t*
                 bad_code = true;
                 qc = 0;
             }
-            qcr[r] = qc;
             tabr[r] = step_tab + qc * kNumSym;
-            E[r] = kNegKey32;                         // E left of the box cannot exist
-            Hleft[r] = gap_key32(go, ge, i0 + r);     // H left of the box: a leading gap of i + 1
+            E[r] = K::kNeg;                      // E left of the box cannot exist
+            Hleft[r] = K::gap(go, ge, i0 + r);   // H left of the box: a leading gap of i + 1
         }
         // lane 0's first diagonal: the origin (strip 0) or the column left of the box
-        int32_t diag_next = (lane == 0) ? (st == 0 ? 0 : gap_key32(go, ge, base - 1)) : kNegKey32;
-        int32_t outH = kNegKey32, outF = kNegKey32;
+        T diag_next = K::kNeg;
+        if (lane == 0) diag_next = st > 0 ? K::gap(go, ge, base - 1) : std::is_same<K, Key32>::value ? (T)0 : (T)kOriginKey;
+        T outH = K::kNeg, outF = K::kNeg;
         uint32_t rc_prev = 0;
         uint32_t cur = code_at(rnib, rhib, R0 + lane);
         uint32_t nxt = code_at(rnib, rhib, R0 + 64 + lane);
         const bool above = st > 0;
-        int32_t curH = 0, curF = 0, nxtH = 0, nxtF = 0;
+        T curH = 0, curF = 0, nxtH = 0, nxtF = 0;
         if (above) {
             curH = Hrow[lane];
             curF = Frow[lane];
@@ -298,17 +340,17 @@ __device__ __forceinline__ int32_t sweep_box32(const int32_t* step_tab, int32_t*
             const uint32_t rc_up = (uint32_t)__shfl_up((int)rc_prev, 1, 64);
             const uint32_t rc = lane == 0 ? rc_new : rc_up;
             rc_prev = rc;
-            int32_t upH = __shfl_up(outH, 1, 64);
-            int32_t upF = __shfl_up(outF, 1, 64);
-            const int32_t topH = (int32_t)readlane32((uint32_t)curH, src);
-            const int32_t topF = (int32_t)readlane32((uint32_t)curF, src);
+            T upH = K::up(outH);
+            T upF = K::up(outF);
+            const T topH = K::lane_value(curH, src);
+            const T topF = K::lane_value(curF, src);
             if (lane == 0) {
                 // the row above: the previous strip's bottom row, or above
                 // the box the keys of a leading gap (no F there)
-                upH = above ? topH : gap_key32(go, ge, t);
-                upF = above ? topF : kNegKey32;
+                upH = above ? topH : K::gap(go, ge, t);
+                upF = above ? topF : K::kNeg;
             }
-            const int32_t diag = diag_next;
+            const T diag = diag_next;
             diag_next = upH;
             const int j = t - lane;
             if (ok0 && j >= 0 && j < N) {
@@ -317,13 +359,13 @@ __device__ __forceinline__ int32_t sweep_box32(const int32_t* step_tab, int32_t*
                     bad_code = true;
                     rcc = 0;
                 }
-                int32_t dg = diag;
+                T dg = diag;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int32_t d = dg + tabr[r][rcc];
-                    E[r] = max(E[r] + GE, Hleft[r] + GO);
-                    const int32_t F = max(upF + GE, upH + GO);
-                    const int32_t H = max(d, max(E[r], F));
+                    const T d = dg + tabr[r][rcc];
+                    E[r] = K::mx(E[r] + GE, Hleft[r] + GO);
+                    const T F = K::mx(upF + GE, upH + GO);
+                    const T H = K::mx(d, K::mx(E[r], F));
                     dg = Hleft[r];
                     Hleft[r] = H;
                     upH = H;
@@ -338,11 +380,11 @@ __device__ __forceinline__ int32_t sweep_box32(const int32_t* step_tab, int32_t*
                 }
             } else if (j == -1) {
                 // the column left of the box, for the next lane's diagonal
-                outH = gap_key32(go, ge, i0 + R - 1);
-                outF = kNegKey32;
+                outH = K::gap(go, ge, i0 + R - 1);
+                outF = K::kNeg;
             } else {
-                outH = kNegKey32;
-                outF = kNegKey32;
+                outH = K::kNeg;
+                outF = K::kNeg;
             }
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the bottom row is in memory
@@ -354,10 +396,12 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
 {
     __shared__ int8_t sub[kNumSym * kNumSym];
     __shared__ int32_t step32[kNumSym * kNumSym];  // diagonal step of a 32-bit key
+    __shared__ int64_t step64[kNumSym * kNumSym];  // and of a 64-bit one
     for (int i = threadIdx.x; i < kNumSym * kNumSym; i += blockDim.x) {
         sub[i] = a.subst[i];
         const int match = (i / kNumSym) == (i % kNumSym) ? 1 : 0;
         step32[i] = ((int32_t)a.subst[i] << kKey32ScoreShift) + (match << kKey32MatchShift) + 1;
+        step64[i] = ((int64_t)a.subst[i] << kScoreShift) + ((int64_t)match << kMatchShift) - 1;
     }
     __syncthreads();
 
@@ -377,10 +421,11 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
     bool bad_range = false, bad_code = false, bad_box = false;
 
     for (;;) {
-        int k = 0;
-        if (lane == 0) k = atomicAdd(a.next_pair, 1);
-        k = __shfl(k, 0, 64);
-        if ((int64_t)k >= a.n_pairs) break;
+        int t = 0;
+        if (lane == 0) t = atomicAdd(a.next_pair, 1);
+        t = __shfl(t, 0, 64);
+        if ((int64_t)t >= a.n_pairs) break;
+        const int k = a.order[t];
         const sw_result res = a.aligned[k];
         sw_identity_result rec = {0, 0, 0, 0};
         bool ok = res.score > 0;
@@ -422,16 +467,16 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
             int32_t* F32 = reinterpret_cast<int32_t*>(Frow);
             int32_t f32;
             if (M <= 64) {
-                f32 = sweep_box32<1>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
-                                     bad_code);
+                f32 = sweep_box_exact<1, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
+                                                R0, lane, bad_code);
                 fin_lane = M - 1;
             } else if (M <= 128) {
-                f32 = sweep_box32<2>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
-                                     bad_code);
+                f32 = sweep_box_exact<2, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
+                                                R0, lane, bad_code);
                 fin_lane = (M - 1) / 2;
             } else {
-                f32 = sweep_box32<4>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
-                                     bad_code);
+                f32 = sweep_box_exact<4, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
+                                                R0, lane, bad_code);
                 fin_lane = ((M - 1) % 256) / 4;
             }
             if (lane == fin_lane) {
@@ -447,7 +492,20 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
             }
             continue;
         }
-        if (M <= 64) {
+        const bool exact = box64x_ok(M, N, a.go, a.ge);
+        if (exact && M <= 64) {
+            fin = sweep_box_exact<1, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
+                                            bad_code);
+            fin_lane = M - 1;
+        } else if (exact && M <= 128) {
+            fin = sweep_box_exact<2, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
+                                            bad_code);
+            fin_lane = (M - 1) / 2;
+        } else if (exact) {
+            fin = sweep_box_exact<4, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
+                                            bad_code);
+            fin_lane = ((M - 1) % 256) / 4;
+        } else if (M <= 64) {
             fin = sweep_box<1>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
             fin_lane = M - 1;
         } else if (M <= 128) {
@@ -458,7 +516,7 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
             fin_lane = ((M - 1) % 256) / 4;
         }
         if (lane == fin_lane) {
-            if (fin >= 0) {
+            if ((fin >> kScoreShift) > 0) {
                 rec.score = (int32_t)(fin >> kScoreShift);
                 rec.matches = (int32_t)((fin >> kMatchShift) & kFieldMask);
                 rec.columns = (int32_t)(kFieldMask - (fin & kFieldMask));
@@ -473,6 +531,65 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
 }
 
 }  // namespace
+
+// Work order: a pair's tier is floor(log2) of its box cells (tier 0 up to
+// 2^10 cells, the last tier from 2^24), pairs without a box in tier 0; the
+// order lists the tiers from the largest down, so the long sweeps start first
+// and the short ones fill the end of the launch.
+__device__ __forceinline__ int box_tier(const IdentArgs& a, int64_t k)
+{
+    const sw_result r = a.aligned[k];
+    if (r.score <= 0) return 0;
+    const int64_t cells = (int64_t)(r.q_end - r.q_start + 1) * (int64_t)(r.r_end - r.r_start + 1);
+    if (cells <= 1024) return 0;
+    const int lg = 63 - __clzll((unsigned long long)cells);
+    return min(lg - 9, kIdentTiers - 1);
+}
+
+__global__ void k_ident_count(IdentArgs a, int32_t* tiers)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
+         k += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&tiers[box_tier(a, k)], 1);
+}
+
+// one thread: cursors start at the tier's place, largest tier first
+__global__ void k_ident_offsets(int32_t* tiers)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int run = 0;
+        for (int t = kIdentTiers - 1; t >= 0; --t) {
+            const int c = tiers[t];
+            tiers[kIdentTiers + t] = run;
+            run += c;
+        }
+    }
+}
+
+__global__ void k_ident_scatter(IdentArgs a, int32_t* tiers, int32_t* order)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int pos = atomicAdd(&tiers[kIdentTiers + box_tier(a, k)], 1);
+        order[pos] = (int32_t)k;
+    }
+}
+
+__global__ void k_ident_zero(int32_t* tiers, int32_t* next_pair)
+{
+    if (threadIdx.x < 2 * kIdentTiers) tiers[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *next_pair = 0;
+}
+
+hipError_t launch_identity_order(const IdentArgs& a, int32_t* tiers, int32_t* order, hipStream_t stream)
+{
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((a.n_pairs + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_ident_zero, dim3(1), dim3(64), 0, stream, tiers, a.next_pair);
+    hipLaunchKernelGGL(k_ident_count, dim3((unsigned)blocks), dim3(256), 0, stream, a, tiers);
+    hipLaunchKernelGGL(k_ident_offsets, dim3(1), dim3(64), 0, stream, tiers);
+    hipLaunchKernelGGL(k_ident_scatter, dim3((unsigned)blocks), dim3(256), 0, stream, a, tiers, order);
+    return hipGetLastError();
+}
 
 hipError_t launch_identity(const IdentArgs& a, int blocks, hipStream_t stream)
 {
