@@ -757,9 +757,17 @@ __device__ __forceinline__ u16x2 max3_u16x2(u16x2 a, u16x2 b, u16x2 c)
 // accesses in order).
 __device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
 
-template <int P, bool REV, bool F16>
+// ONE: the exact cells instead of a pick.  Only super-strip `one_ss` (the
+// one a score-only pass picked; per group) is swept, from the boundary row in
+// buffer `one_buf`, writing nothing; each register keeps, per half (one row),
+// the largest (0xFFFF - column) over the cells that reach `target` -- the
+// pass's values never exceed it, so sat(H - (target - 1)) is 1 exactly there
+// -- which gives every row's first such column, and the group's first row
+// with one is the cell the int32 recompute with trackers would report.
+template <int P, bool REV, bool F16, bool ONE = false>
 __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, uint32_t* xw, uint32_t* __restrict__ slot,
-                                  int64_t Q0, int M, int64_t R0, int N, int target)
+                                  int64_t Q0, int M, int64_t R0, int N, int target, int one_ss = -1,
+                                  int one_buf = 0, Best* one_out = nullptr)
 {
     constexpr int G = kWave / P;
     const int64_t BW = narrow_buf_words(P, N);
@@ -774,6 +782,7 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
     const int wss = uni(wave_max(my_ss));
     const int wc = uni(wave_max(my_ss > 0 ? my_chunks : 0));
     bool done = my_ss == 0 || (REV && target <= 0);
+    const bool one_ok = ONE && target > 0 && one_ss >= 0 && one_ss < my_ss;
     const SeqView qv = seq_view(a.qblk, a.qhdr, Q0);
     const SeqView rv = seq_view(a.rblk, a.rhdr, R0);
     uint32_t* grp_slot = slot + 8 * g;  // [buffer][chunk][group][8 cells]
@@ -816,12 +825,20 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             rqq[k8] = q;
         }
     };
-    row_raw(my_ss > 0 ? 16 * u : M);
+    if constexpr (ONE) row_raw(one_ok ? one_ss * 16 * P + 16 * u : M);
+    else row_raw(my_ss > 0 ? 16 * u : M);
+    const unsigned short tm1s = (unsigned short)max(target - 1, 0);
+    const u16x2 tm1 = {tm1s, tm1s};  // ONE: a cell reaches the target when sat(H - tm1) is 1
+    uint32_t Trk[8];                  // ONE: per row, the largest 0xFFFF - column that reaches it
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Trk[i] = 0;
+    if constexpr (ONE) *one_out = Best{0, -1, -1};
 #pragma unroll 1
-    for (int ss = 0; ss < wss; ++ss) {
-        if (__ballot(!done && ss < my_ss) == 0) break;
-        const bool gact = !done && ss < my_ss;
-        const int row0 = ss * 16 * P + 16 * u;
+    for (int ss = 0; ss < (ONE ? 1 : wss); ++ss) {
+        if (__ballot(ONE ? one_ok : (!done && ss < my_ss)) == 0) break;
+        const bool gact = ONE ? one_ok : (!done && ss < my_ss);
+        const int sv = ONE ? one_ss : ss;  // super-strip index (per group in ONE)
+        const int row0 = sv * 16 * P + 16 * u;
         {
             uint32_t qc[16];
             const int r0 = gact ? row0 : M;
@@ -839,10 +856,11 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             }
             build_profile<16>(prof, lane, qc);
         }
-        const bool read_top = ss > 0;
-        const bool write_next = ss + 1 < my_ss;
+        const bool read_top = sv > 0;
+        const bool write_next = !ONE && ss + 1 < my_ss;
         // the first super-strip reads zeros (one 32-byte row for all chunks)
-        const uint4* in4 = read_top ? reinterpret_cast<const uint4*>(grp_slot + bi * BW) : g_zero_row;
+        const int in_buf = ONE ? min(max(one_buf, 0), 2) : bi;
+        const uint4* in4 = read_top ? reinterpret_cast<const uint4*>(grp_slot + in_buf * BW) : g_zero_row;
         const int in_stride = read_top ? G * 2 : 0;
         uint4* out4 = reinterpret_cast<uint4*>(grp_slot + bo * BW);
         uint32_t H[8], E[8], Mx[4];  // Mx[k]: running maximum of registers 2k and 2k + 1
@@ -927,7 +945,7 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             load_batch(1);
             window_lds(0);
         }
-        row_raw(ss + 1 < my_ss ? row0 + 16 * P : M);
+        if constexpr (!ONE) row_raw(ss + 1 < my_ss ? row0 + 16 * P : M);
         // Iteration t: lane u on chunk c = t - u, A on columns 8c .. 8c+7,
         // B on 8c-1 .. 8c+6.  Each lane needs my_chunks + 1 chunk iterations
         // (the last one for B's final column); the very last iteration of the
@@ -936,6 +954,7 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             constexpr int STEPS = decltype(steps_tag)::value;
             const int c = t - u;
             const bool act = gact && c >= 0 && c <= my_chunks;
+            const int tag0 = 0xFFFF - 8 * c;  // ONE: tag of column 8c (A); B is one column behind
             uint32_t top[8] = {tn0.x, tn0.y, tn0.z, tn0.w, tn1.x, tn1.y, tn1.z, tn1.w};
             if constexpr (P > 1) {
                 // both sources are read and the values selected (a select of
@@ -1026,8 +1045,17 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                     const u16x2 hg = __builtin_elementwise_sub_sat(h, go2);
                     E[i] = as_u32(__builtin_elementwise_max(__builtin_elementwise_sub_sat(as_u16x2(E[i]), ge2), hg));
                     Fv = as_u32(__builtin_elementwise_max(__builtin_elementwise_sub_sat(as_u16x2(Fv), ge2), hg));
-                    if (i & 1) Mx[i / 2] = as_u32(max3_u16x2<F16>(as_u16x2(Mx[i / 2]), h_even, h));
-                    else h_even = h;
+                    if constexpr (!ONE) {
+                        if (i & 1) Mx[i / 2] = as_u32(max3_u16x2<F16>(as_u16x2(Mx[i / 2]), h_even, h));
+                        else h_even = h;
+                    }
+                }
+                if constexpr (ONE) {
+                    const u16x2 tg = {(unsigned short)(tag0 - k), (unsigned short)(tag0 - k + 1)};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        Trk[i] = as_u32(__builtin_elementwise_max(
+                            as_u16x2(Trk[i]), __builtin_elementwise_sub_sat(as_u16x2(H[i]), tm1) * tg));
                 }
                 fo_prev = Fv;
                 up_prev = up_cur;
@@ -1083,6 +1111,20 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         for (int t = 0; t < T - 1; ++t) iteration(t, std::integral_constant<int, 8>());
         iteration(T - 1, std::integral_constant<int, 1>());
         block_fence();
+        if constexpr (ONE) {
+            // the lane's first row with a cell at the target, then the
+            // group's first (rows 0-7 in the low halves, 8-15 in the high)
+            Best b{0, -1, -1};
+            if (gact) {
+#pragma unroll
+                for (int r = 15; r >= 0; --r) {
+                    const uint32_t v = r < 8 ? (Trk[r] & 0xFFFFu) : (Trk[r - 8] >> 16);
+                    if (v != 0 && row0 + r < M) b = Best{target, row0 + r, 0xFFFF - (int)v};
+                }
+            }
+            *one_out = group_best<P>(b);
+            return pick;
+        }
         uint32_t m2 = Mx[0];
 #pragma unroll
         for (int i = 1; i < 4; ++i) m2 = as_u32(__builtin_elementwise_max(as_u16x2(m2), as_u16x2(Mx[i])));
@@ -1224,7 +1266,11 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
             const bool f16 = P == 1 || uni(wave_max(11 * min(m, n))) <= kF16MaxScore;
             const StripPick pf = f16 ? packed_sweep<P, false, true>(a, prof, xw, slot, qoff, m, roff, n, 0)
                                      : packed_sweep<P, false, false>(a, prof, xw, slot, qoff, m, roff, n, 0);
-            f = group_sweep<R, P, false, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, pf.ss, pf.buf);
+            // the first cell of the best score, in the super-strip picked
+            if (f16)
+                packed_sweep<P, false, true, true>(a, prof, xw, slot, qoff, m, roff, n, pf.s, pf.ss, pf.buf, &f);
+            else
+                packed_sweep<P, false, false, true>(a, prof, xw, slot, qoff, m, roff, n, pf.s, pf.ss, pf.buf, &f);
             forward_done(pf.s);
             if (a.phase == 1) return;
         }
@@ -1235,8 +1281,11 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
         const bool f16 = P == 1 || uni(wave_max(f.s)) <= kF16MaxScore;
         const StripPick pr = f16 ? packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s)
                                  : packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
-        const Best r = group_sweep<R, P, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s,
-                                                           hs ? pr.ss : -1, pr.buf);
+        Best r{0, -1, -1};
+        if (f16)
+            packed_sweep<P, true, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1, pr.buf, &r);
+        else
+            packed_sweep<P, true, false, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1, pr.buf, &r);
         if (pid >= 0 && u == 0) {
             if (hs && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
             write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
@@ -1268,11 +1317,15 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
             if constexpr (R == 16) packed_start = uni(f.s) <= kPackedMaxScore && uni(nr) <= kNarrowMaxCols;
             if (packed_start) {
                 uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
-                const StripPick pr = uni(f.s) <= kF16MaxScore
-                                         ? packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s)
-                                         : packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
-                r = group_sweep<R, P, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
-                                                         pr.buf);
+                if (uni(f.s) <= kF16MaxScore) {
+                    const StripPick pr = packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+                    packed_sweep<P, true, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                      pr.buf, &r);
+                } else {
+                    const StripPick pr = packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+                    packed_sweep<P, true, false, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                       pr.buf, &r);
+                }
             } else {
                 StripPick pr{0, -1, 0};
                 group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr);
