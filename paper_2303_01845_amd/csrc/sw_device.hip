@@ -442,10 +442,13 @@ struct StripPick {
 // forward, the first one that reaches the best score, its input row kept; REV,
 // the first one whose maximum reaches `target`.  Padding cells stay below the
 // pair's maximum, so they cannot change either choice.
+//
+// A scan may start at super-strip `ss0` > 0, its input row in buffer `buf0`
+// (the forward scan that continues a packed pass which ran out of 16 bits).
 template <int R, int P, bool REV, bool WIDE, bool ONE = false, bool SCAN = false>
 __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4* xbuf, uint32_t* __restrict__ slot,
                             int64_t Q0, int M, int64_t R0, int N, int target, int one_ss = -1, int one_buf = 0,
-                            StripPick* pick_out = nullptr)
+                            StripPick* pick_out = nullptr, int ss0 = 0, int buf0 = 0)
 {
     static_assert(!SCAN || (WIDE && !ONE), "the scan is the whole-wave path's score pass");
     const int64_t BUFW = WIDE ? wide_buf_words(N) : narrow_buf_words(P, N);
@@ -467,13 +470,19 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
     const SeqView qv = seq_view(a.qblk, a.qhdr, Q0);
     const SeqView rv = seq_view(a.rblk, a.rhdr, R0);
     uint4* slot4 = reinterpret_cast<uint4*>(slot + (ONE ? (int64_t)min(max(one_buf, 0), 2) * BUFW : 0)) + SW * g;
-    int bi = 0, bo = 1, bk = 2;  // SCAN: boundary buffers input, output, kept (uniform in the group)
+    // SCAN: boundary buffers input, output, kept (uniform in the group)
+    int bi = 0, bo = 1, bk = 2;
+    if constexpr (SCAN) {
+        bi = buf0;
+        bo = buf0 == 0 ? 1 : 0;
+        bk = 3 - bi - bo;
+    }
     StripPick pick{0, -1, 0};
     uint4* x_mine = xbuf + SW * lane;
     const uint4* x_up = xbuf + SW * (lane > 0 ? lane - 1 : 0);
 
 #pragma unroll 1
-    for (int ss = 0; ss < wss; ++ss) {
+    for (int ss = SCAN ? ss0 : 0; ss < wss; ++ss) {
         if (__ballot(!done && ss < my_ss) == 0) break;
         const bool gact = !done && ss < my_ss;
         const int sv = ONE ? one_ss : ss;  // super-strip index
@@ -1038,7 +1047,10 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 u16x2 h_even = {0, 0};
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const u16x2 d = __builtin_elementwise_sub_sat(as_u16x2(hd) + as_u16x2(sw[i]), bias2);
+                    // saturating: a value beyond 16 bits stays at 65535 (a pass
+                    // that reaches it gives up, see the strip maximum below)
+                    const u16x2 d = __builtin_elementwise_sub_sat(
+                        __builtin_elementwise_add_sat(as_u16x2(hd), as_u16x2(sw[i])), bias2);
                     const u16x2 h = max3_u16x2<F16>(d, as_u16x2(E[i]), as_u16x2(Fv));
                     hd = H[i];
                     H[i] = as_u32(h);
@@ -1132,7 +1144,15 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
 #pragma unroll
         for (int o = 1; o < P; o <<= 1) smax = max(smax, __shfl_xor(smax, o, kWave));
         if (gact) {
-            if (REV) {
+            if (!REV && smax > kPackedMaxScore) {
+                // some value may not fit 16 bits: the pair continues in int32
+                // from this super-strip, whose input row (every value of the
+                // super-strips above is exact) stays in buffer bi
+                pick.s = -1;
+                pick.ss = ss;
+                pick.buf = bi;
+                done = true;
+            } else if (REV) {
                 if (smax >= target) {
                     pick.ss = ss;
                     pick.buf = bi;
@@ -1158,6 +1178,35 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         }
     }
     return pick;
+}
+
+// Whole wave: copy the narrow boundary row in buffer `nbuf` (one word per
+// column, H | F << 16) into a wide buffer of the same slot (two words per
+// column, H then F), for an int32 scan to continue from.  The wide buffer is
+// the first of the three whose words do not overlap the narrow one's (a wide
+// buffer is at least as long, so the narrow one meets at most two); returns
+// its index.  Not inlined: the copy runs once per pair that overflows, and
+// inlined its registers pushed the persistent kernel into spilling.
+__device__ __attribute__((noinline)) int widen_row(uint32_t* __restrict__ slot, int nbuf, int N)
+{
+    const int64_t BW = narrow_buf_words(kWave, N), WBW = wide_buf_words(N);
+    const int64_t lo = (int64_t)nbuf * BW, hi = lo + BW;
+    int k = 0;
+    while (k < 2 && (int64_t)k * WBW < hi && lo < (int64_t)(k + 1) * WBW) ++k;
+    const uint4* src = reinterpret_cast<const uint4*>(slot + lo);
+    uint4* dst = reinterpret_cast<uint4*>(slot + (int64_t)k * WBW);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int chunks = (N + 7) / 8;
+#pragma unroll 1
+    for (int c = lane; c < chunks; c += kWave) {
+        const uint4 a0 = src[2 * c], a1 = src[2 * c + 1];
+        const uint32_t v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            dst[4 * c + q] = make_uint4(v[2 * q] & 0xFFFFu, v[2 * q] >> 16, v[2 * q + 1] & 0xFFFFu, v[2 * q + 1] >> 16);
+    }
+    block_fence();
+    return k;
 }
 
 // ------------------------------------------------------------------ per-item drivers
@@ -1292,52 +1341,88 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
         }
         return;
     }
-    // whole wave: an int32 scan keeping only each super-strip's maximum, then
-    // the exact cells from one super-strip with trackers -- when three
-    // boundary buffers of the pair fit the slot (pairs up to ~32k columns);
-    // longer ones run the in-place sweep with trackers in every cell
+    // whole wave, pairs beyond kMaxP16Len.  Forward: a packed pass first (its
+    // additions saturate, so any value beyond 16 bits shows as a strip
+    // maximum above kPackedMaxScore and the pass stops there), then the
+    // exact cells from the packed super-strip.  A pass that stopped goes on
+    // as an int32 scan from the super-strip where it stopped (its input row
+    // widened), keeping only each super-strip's maximum, then the exact cells
+    // from one super-strip with trackers -- when three int32 boundary
+    // buffers of the pair fit the slot (pairs up to ~32k columns); else the
+    // in-place sweep with trackers in every cell, from the top.  The start
+    // pass the same way, packed when the score fits.
     if constexpr (WIDE) {
-        if (3 * wide_buf_words(n) <= a.slot_words) {
-            if (a.phase != 2) {
+        const bool scan_fits = 3 * wide_buf_words(n) <= a.slot_words;
+        const bool narrow_ok = R == 16 && uni(n) <= kNarrowMaxCols;  // three narrow buffers always fit
+        if (a.phase != 2) {
+            bool fwd = false;
+            int ss0 = 0, buf0 = 0;  // where an int32 scan starts
+            if constexpr (R == 16) {
+                if (narrow_ok) {
+                    uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
+                    const StripPick pf = packed_sweep<P, false, false>(a, prof, xw, slot, qoff, m, roff, n, 0);
+                    if (uni(pf.s) >= 0) {
+                        packed_sweep<P, false, false, true>(a, prof, xw, slot, qoff, m, roff, n, pf.s, pf.ss,
+                                                            pf.buf, &f);
+                        forward_done(pf.s);
+                        fwd = true;
+                    } else if (scan_fits && uni(pf.ss) > 0) {
+                        // every super-strip above pf.ss stayed below
+                        // kPackedMaxScore, so the best score (above it) is
+                        // reached below: the scan goes on from pf.ss
+                        ss0 = uni(pf.ss);
+                        buf0 = widen_row(slot, uni(pf.buf), n);
+                    }
+                }
+            }
+            if (!fwd && scan_fits) {
                 StripPick pf{0, -1, 0};
-                group_sweep<R, P, false, true, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, -1, 0, &pf);
+                group_sweep<R, P, false, true, false, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, -1, 0, &pf,
+                                                            ss0, buf0);
                 f = group_sweep<R, P, false, true, true>(a, prof, xbuf, slot, qoff, m, roff, n, 0, pf.ss, pf.buf);
                 forward_done(pf.s);
-                if (a.phase == 1) return;
+                fwd = true;
             }
-            const bool hs = f.s > 0;
-            const int64_t qr = qoff + (hs ? f.i : 0), rr = roff + (hs ? f.j : 0);
-            const int mr = hs ? f.i + 1 : 0, nr = hs ? f.j + 1 : 0;
-            Best r{0, -1, -1};
-            // Every value of the start pass is at most the score, so when the
-            // score (plus the 15 of a biased substitution score) fits 16 bits
-            // the pass runs in packed cells, and its recompute in narrow
-            // cells whose 16-bit column tags cover the region's columns.
-            bool packed_start = false;
-            if constexpr (R == 16) packed_start = uni(f.s) <= kPackedMaxScore && uni(nr) <= kNarrowMaxCols;
-            if (packed_start) {
-                uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
-                if (uni(f.s) <= kF16MaxScore) {
-                    const StripPick pr = packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
-                    packed_sweep<P, true, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
-                                                      pr.buf, &r);
-                } else {
-                    const StripPick pr = packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
-                    packed_sweep<P, true, false, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
-                                                       pr.buf, &r);
-                }
-            } else {
-                StripPick pr{0, -1, 0};
-                group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr);
-                r = group_sweep<R, P, true, true, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
-                                                        pr.buf);
+            if (!fwd) {
+                f = group_sweep<R, P, false, WIDE>(a, prof, xbuf, slot, qoff, m, roff, n, 0);
+                forward_done(-1);
             }
-            if (pid >= 0 && u == 0) {
-                if (hs && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
-                write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
-            }
-            return;
+            if (a.phase == 1) return;
         }
+        const bool hs = f.s > 0;
+        const int64_t qr = qoff + (hs ? f.i : 0), rr = roff + (hs ? f.j : 0);
+        const int mr = hs ? f.i + 1 : 0, nr = hs ? f.j + 1 : 0;
+        Best r{0, -1, -1};
+        // Every value of the start pass is at most the score, so when the
+        // score (plus the 15 of a biased substitution score) fits 16 bits
+        // the pass runs in packed cells, and its recompute in narrow
+        // cells whose 16-bit column tags cover the region's columns.
+        bool packed_start = false;
+        if constexpr (R == 16) packed_start = uni(f.s) <= kPackedMaxScore && uni(nr) <= kNarrowMaxCols;
+        if (packed_start) {
+            uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
+            if (uni(f.s) <= kF16MaxScore) {
+                const StripPick pr = packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+                packed_sweep<P, true, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                  pr.buf, &r);
+            } else {
+                const StripPick pr = packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+                packed_sweep<P, true, false, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                   pr.buf, &r);
+            }
+        } else if (scan_fits) {
+            StripPick pr{0, -1, 0};
+            group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr);
+            r = group_sweep<R, P, true, true, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                    pr.buf);
+        } else {
+            r = group_sweep<R, P, true, WIDE>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s);
+        }
+        if (pid >= 0 && u == 0) {
+            if (hs && r.s != f.s) atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
+            write_result(a.out, pid, f.s, f.i - r.i, f.i, f.j - r.j, f.j);
+        }
+        return;
     }
     if (a.phase != 2) {
         f = group_sweep<R, P, false, WIDE>(a, prof, xbuf, slot, qoff, m, roff, n, 0);

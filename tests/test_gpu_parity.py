@@ -214,6 +214,60 @@ def test_maximum_length_pairs(sw):
     assert_same(gpu_align(sw, ps), expect(ps), ps, "max length")
 
 
+def _self_score_sequence(rng, M, target, length_hint=14000):
+    """A sequence whose BLOSUM62 self-score (the sum of its diagonal entries)
+    is exactly `target`: a background prefix, then residues of diagonal score
+    4 and one of 4..7 to make up the rest."""
+    a = P.background(rng, length_hint)
+    d = M[oracle.encode(a), oracle.encode(a)].astype(np.int64)
+    cut = int(np.searchsorted(np.cumsum(d), target - 40))
+    rest = target - int(d[:cut].sum())
+    k, rem = divmod(rest, 4)
+    fill = {4: "A", 5: "R", 6: "N", 7: "P"}
+    for v, ch in fill.items():
+        c = int(oracle.encode(np.frombuffer(ch.encode(), dtype=np.uint8))[0])
+        assert M[c, c] == v
+    tail = "A" * (k - 1) + fill[4 + rem]
+    return np.concatenate([a[:cut], np.frombuffer(tail.encode(), dtype=np.uint8)])
+
+
+def test_packed_overflow_long_pairs(sw):
+    # Whole-wave pairs run their forward pass in 16-bit cells with saturating
+    # additions and fall back to int32 when a strip's maximum passes 65504.
+    # Identical pairs with self-scores on either side of that limit (and of
+    # the 16-bit ceiling), plus mutated pairs with gaps, all beyond the
+    # 4096-residue packed limit of the smaller groups.
+    rng = np.random.default_rng(21)
+    M = oracle.matrix()
+    seqs = []
+    for t in (65503, 65504, 65505, 65535, 65536, 65540):
+        x = _self_score_sequence(rng, M, t)
+        seqs += [x, x.copy()]
+    for L, rate in [(11000, 0.02), (12500, 0.01), (13400, 0.03), (16000, 0.05)]:
+        a = P.background(rng, L)
+        b = a.copy()
+        hit = rng.random(L) < rate
+        b[hit] = P.background(rng, int(hit.sum()))
+        for _ in range(6):
+            p = int(rng.integers(100, len(b) - 100))
+            if rng.random() < 0.5:
+                b = np.concatenate([b[:p], P.background(rng, int(rng.integers(1, 12))), b[p:]])
+            else:
+                b = np.concatenate([b[:p], b[p + int(rng.integers(1, 12)):]])
+        seqs += [a, b]
+    L = np.array([len(s) for s in seqs], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(L)])
+    n = len(seqs) // 2
+    pairs = np.arange(2 * n, dtype=np.int32).reshape(-1, 2)
+    pairs = np.concatenate([pairs, pairs[:, ::-1]]).astype(np.int32)
+    ps = P.PairSet(np.concatenate(seqs), offs, pairs, "overflow")
+    exp = expect(ps)
+    assert exp[:6, 0].tolist() == [65503, 65504, 65505, 65535, 65536, 65540]
+    assert (exp[:, 0] <= 65504).sum() >= 4 and (exp[:, 0] > 65504).sum() >= 4
+    say("packed overflow: %d pairs, scores %s" % (ps.n_pairs, exp[:n, 0].tolist()))
+    assert_same(gpu_align(sw, ps), exp, ps, "packed overflow")
+
+
 def test_two_sets_match_one_set(sw):
     import torch
     ps = P.config_small(300)
