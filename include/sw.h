@@ -281,11 +281,15 @@ SW_API int sw_get_tuning(sw_tuning* t);
  * one pair (the paper balances its alignment work by the cost of each pair,
  * m*n, section "Load balancing techniques").
  * For rows_per_lane 16 and 8 (the occupancy-derived grid), every length
- * bucket that holds pairs of this workload is timed alone -- the persistent
- * form over that bucket's pairs, one untimed call then `reps` timed ones --
- * with each lane count the bucket allows (1, 8, 16, 64), and keeps the
- * fastest; then the whole workload is timed with each rows_per_lane and its
- * table, and the faster becomes the current tuning (sw_get_tuning shows it).
+ * bucket that holds pairs of this workload is timed alone with each lane
+ * count the bucket allows (1, 8, 16, 64), and keeps the fastest.  A bucket
+ * is timed on a filled device: the persistent form over its pairs repeated
+ * until a call holds at least 4e9 cells and four one-lane items per block
+ * (at most 1.6e10 cells and 2^21 pairs), one untimed call then `reps` timed
+ * ones.  Then the
+ * whole workload is timed with the current tuning and with each
+ * rows_per_lane and its table; the fastest of the three becomes the current
+ * tuning (sw_get_tuning shows it).
  * Every candidate must give byte-identical results (else SW_EDEVICE and the
  * previous tuning is restored).  out_dev receives the results of the whole
  * workload under the chosen tuning.

@@ -2,6 +2,7 @@
 // per-device workspace, the work-cell orderings, HIP-graph replay of the
 // persistent form and the per-bucket launch series of the plain form.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -374,7 +375,7 @@ size_t up_ws(size_t b) { return (b + kWsAlign - 1) / kWsAlign * kWsAlign; }
 size_t ws_head_bytes(int64_t n_pairs)
 {
     const size_t np = (size_t)std::max<int64_t>(n_pairs, 1);
-    return up_ws(sizeof(int32_t) * kNumCells * kCellShards) + up_ws(sizeof(int32_t) * (kNumCells + 1)) +
+    return up_ws(sizeof(int32_t) * 2 * kNumCells * kCellShards) + up_ws(sizeof(int32_t) * (kNumCells + 1)) +
            up_ws(sizeof(int32_t) * kNumCounters) + 2 * up_ws(sizeof(int32_t) * np);
 }
 
@@ -399,7 +400,7 @@ int carve_workspace(void* base, size_t bytes, int64_t n_pairs, int max_grid, WsV
         return reinterpret_cast<int32_t*>(q);
     };
     const size_t np = (size_t)std::max<int64_t>(n_pairs, 1);
-    v->cell_count = take(sizeof(int32_t) * kNumCells * kCellShards);
+    v->cell_count = take(sizeof(int32_t) * 2 * kNumCells * kCellShards);
     v->rank_start = take(sizeof(int32_t) * (kNumCells + 1));
     v->counters = take(sizeof(int32_t) * kNumCounters);
     v->pair_cell = take(sizeof(int32_t) * np);
@@ -418,7 +419,8 @@ int library_workspace(Workspace& w, int64_t n_pairs, int grid, WsView* v)
     bool changed = false;
     if (!w.cell_count) {
         int rc;
-        if ((rc = grow(&w.cell_count, (int64_t)kNumCells * kCellShards)) || (rc = grow(&w.rank_start, kNumCells + 1)) ||
+        if ((rc = grow(&w.cell_count, (int64_t)2 * kNumCells * kCellShards)) ||
+            (rc = grow(&w.rank_start, kNumCells + 1)) ||
             (rc = grow(&w.counters, kNumCounters)))
             return rc;
         changed = true;
@@ -678,7 +680,8 @@ void fill_args(Args& a, const Device& d, const WsView& v, const void* q_packed_d
     a.out = out_dev;
     a.pair_cell = v.pair_cell;
     a.perm = v.perm;
-    a.cell_count = v.cell_count;
+    a.cell_count = v.cell_count;  // two histograms: forward, then start passes
+    a.cell_count_next = v.cell_count + (int64_t)kNumCells * kCellShards;
     a.rank_start = v.rank_start;
     a.counters = v.counters;
     a.err = d.err;
@@ -750,6 +753,7 @@ int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n
         Args a1 = a, a2 = a;
         a1.phase = 1;
         a2.phase = 2;
+        a2.cell_count = a.cell_count_next;
         HIP_TRY(launch_prepare(a1, stream), "prepare launch");
         HIP_TRY(launch_persistent(a1, v.grid, stream), "persistent launch");
         HIP_TRY(launch_prepare(a2, stream), "prepare launch");
@@ -836,6 +840,7 @@ int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n
         Args a1 = a, a2 = a;
         a1.phase = 1;
         a2.phase = 2;
+        a2.cell_count = a.cell_count_next;
         if (flags & SW_NO_GRAPH) {
             HIP_TRY(launch_prepare(a1, stream), "prepare launch");
             HIP_TRY(begin_timed(0), "hipEventRecord");
@@ -1525,8 +1530,30 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
         v.push_back((int32_t)qi);
         v.push_back((int32_t)ri);
     }
+    // A bucket is timed on a filled device: its pairs repeated until one call
+    // holds at least kTuneMinCells cells and kTuneMinItems one-lane items of
+    // every block (a bucket's own few pairs would time the launch's tail,
+    // where the widest groups always win, not the rate it runs at inside the
+    // whole workload), as far as kTuneMaxCells cells and kTuneMaxPairs pairs
+    // allow (buckets of long pairs fill the device with few of them).
+    constexpr double kTuneMinCells = 4e9, kTuneMaxCells = 1.6e10;
+    constexpr int64_t kTuneMinItems = 4, kTuneMaxPairs = int64_t(1) << 21;
+    const int64_t min_pairs = (int64_t)n_cu * bpc * kWave * kTuneMinItems;
     size_t most = 1;
-    for (const auto& v : by_bucket) most = std::max(most, v.size() / 2);
+    for (auto& v : by_bucket) {
+        const int64_t np = (int64_t)v.size() / 2;
+        if (np == 0) continue;
+        double cells = 0;
+        for (int64_t k = 0; k < np; ++k)
+            cells += (double)(offs[v[2 * k] + 1] - offs[v[2 * k]]) * (double)(offs[v[2 * k + 1] + 1] - offs[v[2 * k + 1]]);
+        int64_t copies = std::max<int64_t>((int64_t)std::ceil(kTuneMinCells / cells), (min_pairs + np - 1) / np);
+        copies = std::min<int64_t>(copies, (int64_t)(kTuneMaxCells / cells));
+        copies = std::max<int64_t>(1, std::min(copies, kTuneMaxPairs / np));
+        const size_t one = v.size();
+        v.resize(one * (size_t)copies);
+        for (int64_t c = 1; c < copies; ++c) std::copy(v.begin(), v.begin() + one, v.begin() + one * c);
+        most = std::max(most, v.size() / 2);
+    }
     std::vector<TuneEntry> cache;
     if (cache_path) cache = read_tune_cache(cache_path);
     const TuneEntry key0{arch, n_cu, bpc, 0, scoring->gap_open, scoring->gap_extend, 0, 0, 0.f};
@@ -1577,6 +1604,18 @@ int sw_autotune(const void* packed_dev, const int64_t* offsets_dev, int64_t n_se
     float best = 1e30f;
     sw_tuning best_t = orig;
     std::vector<sw_result> full_ref;
+    // the current tuning is a candidate too: the tuner never returns a table
+    // slower than it on this workload
+    {
+        sw_tuning t = orig;
+        t.blocks_per_cu = -1;
+        if ((rc = trial(t, pairs_dev, n_pairs, out_dev, full_ref, &best))) {
+            cleanup();
+            (void)sw_set_tuning(&orig);
+            return rc;
+        }
+        best_t = t;
+    }
     for (int R : {16, 8}) {
         sw_tuning t = orig;
         t.rows_per_lane = R;

@@ -1180,6 +1180,45 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
     return pick;
 }
 
+// ------------------------------------------------------------------ work cells
+__device__ __forceinline__ int ceil_log2(int64_t x)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < x) ++b;
+    return b;
+}
+
+// Lanes per pair of a work cell: 1 for the short-pair cells; for long pairs
+// by length bucket 8 up to group8_max, 16 up to group16_max (both at most
+// kMaxP16Len residues), 64 beyond.
+__device__ __forceinline__ int cell_kind(int cell, const Args& a)
+{
+    if (cell < kInterCells) return 1;
+    const int bucket = (cell - kInterCells) / kWideCostBins;
+    return bucket_group_kind(bucket, a.bucket_kind[bucket], a.group8_max_len, a.group16_max_len);
+}
+
+// Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
+// (length bucket, 16*log2(m*n)).  Returns -1 for pairs that need no work and
+// -2 for invalid pairs (their result is written here).
+// Cell of a pair of lengths m, n > 0 (lane-per-pair cells by (strips,
+// chunks), longer pairs by (length bucket, 16*log2(m*n))).
+__device__ __forceinline__ int cell_of(const Args& a, int64_t m, int64_t n)
+{
+    const int64_t mx = m > n ? m : n;
+    const int ov = a.bucket_kind[ceil_log2(mx)];
+    if (ov == 1 || (ov == 0 && mx <= a.inter_max_len)) {
+        const int s = (int)((m + a.rows_per_lane - 1) / a.rows_per_lane);
+        const int c = (int)((n + 7) / 8);
+        return (s - 1) * kMaxInterChunks + (c - 1);
+    }
+    const int64_t cost = m * n;
+    const int msb = 63 - __clzll((unsigned long long)cost);
+    const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15) : 0;
+    const int cb = min(kWideCostBins - 1, 16 * msb + frac);
+    return kInterCells + ceil_log2(mx) * kWideCostBins + cb;
+}
+
 // Whole wave: copy the narrow boundary row in buffer `nbuf` (one word per
 // column, H | F << 16) into a wide buffer of the same slot (two words per
 // column, H then F), for an int32 scan to continue from.  The wide buffer is
@@ -1277,6 +1316,7 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
                 sw_result bad;
                 bad.score = bad.q_start = bad.q_end = bad.r_start = bad.r_end = -1;
                 a.out[pid] = bad;
+                if (a.phase == 1) a.pair_cell[pid] = -1;  // no start pass
             }
             pid = -1;
             m = n = 0;
@@ -1287,6 +1327,9 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     uint4* xbuf = reinterpret_cast<uint4*>(lds + kNumCodes * kWave * prof_bytes(R));
     // forward pass done: phase 1 stores score and end, the start pass follows
     // in phase 0
+    // in phase 0.  Phase 1 also sorts the pair for its start pass: the cell of
+    // the region q[0..end] x r[0..end] (none at score 0) into pair_cell and
+    // the start passes' histogram, so that their launch needs no classify.
     auto forward_done = [&](int packed_s) __attribute__((always_inline)) {
         if (pid >= 0 && u == 0 && packed_s >= 0 && f.s != packed_s)
             atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
@@ -1297,6 +1340,9 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
             r.q_end = f.s > 0 ? f.i : -1;
             r.r_end = f.s > 0 ? f.j : -1;
             a.out[pid] = r;
+            const int cell = f.s > 0 && f.i >= 0 && f.j >= 0 ? cell_of(a, (int64_t)f.i + 1, (int64_t)f.j + 1) : -1;
+            a.pair_cell[pid] = cell;
+            if (cell >= 0) atomicAdd(&a.cell_count_next[cell * kCellShards + pid % kCellShards], 1);
         }
     };
     // packed score passes for every pair up to kMaxP16Len residues (the one-,
@@ -1537,55 +1583,7 @@ __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, uint32_t* _
     if (bad) atomicOr((unsigned*)err, (unsigned)kErrCode);
 }
 
-// ------------------------------------------------------------------ work cells
-__device__ __forceinline__ int ceil_log2(int64_t x)
-{
-    int b = 0;
-    while (((int64_t)1 << b) < x) ++b;
-    return b;
-}
-
-// Lanes per pair of a work cell: 1 for the short-pair cells; for long pairs
-// by length bucket 8 up to group8_max, 16 up to group16_max (both at most
-// kMaxP16Len residues), 64 beyond.
-__device__ __forceinline__ int cell_kind(int cell, const Args& a)
-{
-    if (cell < kInterCells) return 1;
-    const int bucket = (cell - kInterCells) / kWideCostBins;
-    return bucket_group_kind(bucket, a.bucket_kind[bucket], a.group8_max_len, a.group16_max_len);
-}
-
-// Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
-// (length bucket, 16*log2(m*n)).  Returns -1 for pairs that need no work and
-// -2 for invalid pairs (their result is written here).
-// Cell of a pair of lengths m, n > 0 (lane-per-pair cells by (strips,
-// chunks), longer pairs by (length bucket, 16*log2(m*n))).
-__device__ __forceinline__ int cell_of(const Args& a, int64_t m, int64_t n)
-{
-    const int64_t mx = m > n ? m : n;
-    const int ov = a.bucket_kind[ceil_log2(mx)];
-    if (ov == 1 || (ov == 0 && mx <= a.inter_max_len)) {
-        const int s = (int)((m + a.rows_per_lane - 1) / a.rows_per_lane);
-        const int c = (int)((n + 7) / 8);
-        return (s - 1) * kMaxInterChunks + (c - 1);
-    }
-    const int64_t cost = m * n;
-    const int msb = 63 - __clzll((unsigned long long)cost);
-    const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15) : 0;
-    const int cb = min(kWideCostBins - 1, 16 * msb + frac);
-    return kInterCells + ceil_log2(mx) * kWideCostBins + cb;
-}
-
-// Start-pass cell of a pair whose forward pass is done: by the reversed
-// prefixes q[0..q_end], r[0..r_end]; -1 when there is nothing to do (score 0,
-// or a pair the forward pass rejected).
-__device__ __forceinline__ int classify_start(const Args& a, int64_t k)
-{
-    const sw_result r = a.out[k];
-    if (r.score <= 0 || r.q_end < 0 || r.r_end < 0) return -1;
-    return cell_of(a, (int64_t)r.q_end + 1, (int64_t)r.r_end + 1);
-}
-
+// ------------------------------------------------------------------ counting sort into cells
 __device__ __forceinline__ int classify(const Args& a, int64_t k)
 {
     const int64_t qi = a.pairs[2 * k], ri = a.pairs[2 * k + 1];
@@ -1620,8 +1618,10 @@ __global__ void k_fill(int32_t* p, int64_t n, int32_t v)
 
 __global__ void k_zero_cells(Args a)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNumCells * kCellShards; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNumCells * kCellShards; i += gridDim.x * blockDim.x) {
         a.cell_count[i] = 0;
+        a.cell_count_next[i] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntHead] = 0;
 }
 
@@ -1629,32 +1629,32 @@ __global__ void k_prepare(Args a)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int cell = a.phase == 2 ? classify_start(a, k) : classify(a, k);
+        const int cell = classify(a, k);
         a.pair_cell[k] = cell;
         if (cell >= 0) atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1);
         else if (cell == -2) atomicOr((unsigned*)a.err, (unsigned)kErrRange);
     }
 }
 
-// Single block: exclusive scan of the cell counts in rank order (a cell's
-// shards in shard order); the counts become scatter cursors; counters get the
-// number of pairs of each kind.
-__global__ __launch_bounds__(1024) void k_scan(Args a)
+// Exclusive scan of the cell counts in rank order (a cell's shards in shard
+// order): the counts become scatter cursors, rank_start gets the first
+// position of each rank, counters the number of pairs of each kind.  Two
+// launches of kScanTiles blocks: each block sums its tile of kScanRanks
+// ranks (all pairs, and those of 64-, 16- and 8-lane items), then each block
+// scans its tile again from the sum of the tiles before it.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = kScanRanks / kScanThreads;  // ranks per thread
+static_assert(kScanRanks % kScanThreads == 0, "whole ranks per thread");
+static_assert(kCellShards == 16, "a cell's shards are read as four int4");
+
+// this thread's ranks: their cells and counts (all shards)
+__device__ __forceinline__ void scan_load(const Args& a, int tile, int (&cells)[kScanPer], int (&cnt)[kScanPer])
 {
-    __shared__ int part[1024];
-    __shared__ int n64s[1024];
-    __shared__ int n16s[1024];
-    __shared__ int n8s[1024];
-    const int t = threadIdx.x;
-    constexpr int per = (kNumCells + 1023) / 1024;
-    const int lo = t * per, hi = min(kNumCells, lo + per);
-    static_assert(kCellShards == 16, "a cell's shards are read as four int4");
-    // this thread's cells first (independent loads), then their shards, a few
-    // cells at a time so that the loads overlap without spilling
-    int cells[per];
+    const int r0 = tile * kScanRanks + threadIdx.x * kScanPer;
 #pragma unroll
-    for (int i = 0; i < per; ++i) cells[i] = lo + i < hi ? a.rank_cell[lo + i] : 0;
-    auto shard_sum = [&](int i) -> int {
+    for (int i = 0; i < kScanPer; ++i) cells[i] = r0 + i < kNumCells ? a.rank_cell[r0 + i] : 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
         const int4* q = reinterpret_cast<const int4*>(a.cell_count + cells[i] * kCellShards);
         int c = 0;
 #pragma unroll
@@ -1662,40 +1662,72 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
             const int4 x = q[v];
             c += x.x + x.y + x.z + x.w;
         }
-        return lo + i < hi ? c : 0;
-    };
-    int sum = 0, c64 = 0, c16 = 0, c8 = 0;
-#pragma unroll 4
-    for (int i = 0; i < per; ++i) {
-        const int c = shard_sum(i);
-        sum += c;
+        cnt[i] = r0 + i < kNumCells ? c : 0;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Args a)
+{
+    __shared__ int part[kScanThreads / kWave][4];
+    int cells[kScanPer], cnt[kScanPer];
+    scan_load(a, blockIdx.x, cells, cnt);
+    int v[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        v[0] += cnt[i];
         const int kind = cell_kind(cells[i], a);
-        if (kind == 64) c64 += c;
-        else if (kind == 16) c16 += c;
-        else if (kind == 8) c8 += c;
+        v[1] += kind == 64 ? cnt[i] : 0;
+        v[2] += kind == 16 ? cnt[i] : 0;
+        v[3] += kind == 8 ? cnt[i] : 0;
     }
-    part[t] = sum;
-    n64s[t] = c64;
-    n16s[t] = c16;
-    n8s[t] = c8;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) v[k] += __shfl_xor(v[k], o, kWave);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[w][k] = v[k];
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int v = t >= o ? part[t - o] : 0;
-        const int w = t >= o ? n64s[t - o] : 0;
-        const int x = t >= o ? n16s[t - o] : 0;
-        const int y = t >= o ? n8s[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        n64s[t] += w;
-        n16s[t] += x;
-        n8s[t] += y;
-        __syncthreads();
+    if (threadIdx.x < 4) {
+        int t = 0;
+        for (int j = 0; j < kScanThreads / kWave; ++j) t += part[j][threadIdx.x];
+        a.counters[kCntTiles + 4 * blockIdx.x + threadIdx.x] = t;
     }
-    int run = part[t] - sum;  // exclusive prefix
-#pragma unroll 2
-    for (int i = 0; i < per; ++i) {
-        if (lo + i >= hi) break;
-        a.rank_start[lo + i] = run;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(Args a)
+{
+    __shared__ int wsum[kScanThreads / kWave];
+    __shared__ int tile_base;
+    const int tile = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int b = 0;
+        for (int j = 0; j < tile; ++j) b += a.counters[kCntTiles + 4 * j];
+        tile_base = b;
+    }
+    int cells[kScanPer], cnt[kScanPer];
+    scan_load(a, tile, cells, cnt);
+    int mine = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) mine += cnt[i];
+    // inclusive scan over the wave, then over the block's waves
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int inc = mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(inc, o, kWave);
+        inc += lane >= o ? y : 0;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int run = tile_base + inc - mine;
+    for (int j = 0; j < w; ++j) run += wsum[j];
+    const int r0 = tile * kScanRanks + threadIdx.x * kScanPer;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        if (r0 + i >= kNumCells) break;
+        a.rank_start[r0 + i] = run;
         int4* q = reinterpret_cast<int4*>(a.cell_count + cells[i] * kCellShards);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -1709,12 +1741,16 @@ __global__ __launch_bounds__(1024) void k_scan(Args a)
             q[v] = y;
         }
     }
-    if (t == 1023) {
-        a.rank_start[kNumCells] = part[1023];
-        a.counters[kCntP64] = n64s[1023];
-        a.counters[kCntP16] = n16s[1023];
-        a.counters[kCntP8] = n8s[1023];
-        a.counters[kCntP1] = part[1023] - n64s[1023] - n16s[1023] - n8s[1023];
+    if (tile == kScanTiles - 1 && threadIdx.x == 0) {
+        int t[4] = {0, 0, 0, 0};
+        for (int j = 0; j < kScanTiles; ++j)
+            for (int k = 0; k < 4; ++k) t[k] += a.counters[kCntTiles + 4 * j + k];
+        a.rank_start[kNumCells] = t[0];
+        a.counters[kCntP64] = t[1];
+        a.counters[kCntP16] = t[2];
+        a.counters[kCntP8] = t[3];
+        a.counters[kCntP1] = t[0] - t[1] - t[2] - t[3];
+        a.counters[kCntHead] = 0;  // the work queue of the launch that follows
     }
 }
 
@@ -1804,10 +1840,13 @@ hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err,
 
 hipError_t launch_prepare(const Args& a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_zero_cells, dim3(64), dim3(256), 0, stream, a);
     const int64_t blocks = std::min<int64_t>((a.n_pairs + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_prepare, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, a);
+    if (a.phase != 2) {
+        hipLaunchKernelGGL(k_zero_cells, dim3(64), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_prepare, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(kScanTiles), dim3(kScanThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_scan_apply, dim3(kScanTiles), dim3(kScanThreads), 0, stream, a);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

@@ -61,6 +61,11 @@ constexpr int kNumCells = kInterCells + kWideCells;
 // all land on one address.
 constexpr int kCellShards = 16;
 
+// The scan of the cell counts runs over tiles of kScanRanks ranks, one block
+// each, then applies every tile's prefix.
+constexpr int kScanRanks = 1024;
+constexpr int kScanTiles = (kNumCells + kScanRanks - 1) / kScanRanks;
+
 // counters[] slots in the workspace
 enum {
     kCntHead = 0,   // persistent work-queue head
@@ -68,7 +73,8 @@ enum {
     kCntP16 = 2,    // pairs aligned by 16 lanes
     kCntP1 = 3,     // pairs aligned by one lane
     kCntP8 = 4,     // pairs aligned by 8 lanes
-    kNumCounters = 16
+    kCntTiles = 16, // per scan tile: its pairs, and those of 64, 16 and 8 lanes
+    kNumCounters = kCntTiles + 4 * kScanTiles
 };
 enum { kErrRange = 1, kErrCode = 2, kErrInternal = 4 };
 
@@ -87,6 +93,7 @@ struct Args {
     int32_t* pair_cell;        // [n_pairs] work cell of each pair (-1 none, -2 invalid)
     int32_t* perm;             // [n_pairs] pair indices sorted by rank of their cell
     int32_t* cell_count;       // [kNumCells][kCellShards] histogram, then scatter cursors
+    int32_t* cell_count_next;  // the start passes' histogram, counted by the forward launch
     const int32_t* rank_cell;  // [kNumCells] cell at each rank
     int32_t* rank_start;       // [kNumCells + 1] first perm position of each rank
     int32_t* counters;         // [kNumCounters]
@@ -120,7 +127,9 @@ __host__ __device__ inline int bucket_group_kind(int bucket, int override_kind, 
 
 // launchers (sw_device.hip); all asynchronous on `stream`
 hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err, hipStream_t stream);
-hipError_t launch_prepare(const Args& a, hipStream_t stream);  // zero, classify, scan, scatter
+// zero, classify, scan, scatter; for phase 2 (start passes) only scan and
+// scatter: the forward launch classified its pairs into cell_count_next
+hipError_t launch_prepare(const Args& a, hipStream_t stream);
 hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream);
 hipError_t launch_plain(const Args& a, int kind, int first, int count, int grid, hipStream_t stream);
 hipError_t set_kernel_attributes();
