@@ -375,7 +375,7 @@ size_t up_ws(size_t b) { return (b + kWsAlign - 1) / kWsAlign * kWsAlign; }
 size_t ws_head_bytes(int64_t n_pairs)
 {
     const size_t np = (size_t)std::max<int64_t>(n_pairs, 1);
-    return up_ws(sizeof(int32_t) * 2 * kNumCells * kCellShards) + up_ws(sizeof(int32_t) * (kNumCells + 1)) +
+    return up_ws(sizeof(int32_t) * kNumCells * kCellShards) + up_ws(sizeof(int32_t) * (kNumCells + 1)) +
            up_ws(sizeof(int32_t) * kNumCounters) + 2 * up_ws(sizeof(int32_t) * np);
 }
 
@@ -400,7 +400,7 @@ int carve_workspace(void* base, size_t bytes, int64_t n_pairs, int max_grid, WsV
         return reinterpret_cast<int32_t*>(q);
     };
     const size_t np = (size_t)std::max<int64_t>(n_pairs, 1);
-    v->cell_count = take(sizeof(int32_t) * 2 * kNumCells * kCellShards);
+    v->cell_count = take(sizeof(int32_t) * kNumCells * kCellShards);
     v->rank_start = take(sizeof(int32_t) * (kNumCells + 1));
     v->counters = take(sizeof(int32_t) * kNumCounters);
     v->pair_cell = take(sizeof(int32_t) * np);
@@ -419,8 +419,7 @@ int library_workspace(Workspace& w, int64_t n_pairs, int grid, WsView* v)
     bool changed = false;
     if (!w.cell_count) {
         int rc;
-        if ((rc = grow(&w.cell_count, (int64_t)2 * kNumCells * kCellShards)) ||
-            (rc = grow(&w.rank_start, kNumCells + 1)) ||
+        if ((rc = grow(&w.cell_count, (int64_t)kNumCells * kCellShards)) || (rc = grow(&w.rank_start, kNumCells + 1)) ||
             (rc = grow(&w.counters, kNumCounters)))
             return rc;
         changed = true;
@@ -680,8 +679,7 @@ void fill_args(Args& a, const Device& d, const WsView& v, const void* q_packed_d
     a.out = out_dev;
     a.pair_cell = v.pair_cell;
     a.perm = v.perm;
-    a.cell_count = v.cell_count;  // two histograms: forward, then start passes
-    a.cell_count_next = v.cell_count + (int64_t)kNumCells * kCellShards;
+    a.cell_count = v.cell_count;
     a.rank_start = v.rank_start;
     a.counters = v.counters;
     a.err = d.err;
@@ -753,7 +751,6 @@ int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n
         Args a1 = a, a2 = a;
         a1.phase = 1;
         a2.phase = 2;
-        a2.cell_count = a.cell_count_next;
         HIP_TRY(launch_prepare(a1, stream), "prepare launch");
         HIP_TRY(launch_persistent(a1, v.grid, stream), "persistent launch");
         HIP_TRY(launch_prepare(a2, stream), "prepare launch");
@@ -840,7 +837,6 @@ int align_impl(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n
         Args a1 = a, a2 = a;
         a1.phase = 1;
         a2.phase = 2;
-        a2.cell_count = a.cell_count_next;
         if (flags & SW_NO_GRAPH) {
             HIP_TRY(launch_prepare(a1, stream), "prepare launch");
             HIP_TRY(begin_timed(0), "hipEventRecord");

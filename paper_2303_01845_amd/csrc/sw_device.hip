@@ -1144,10 +1144,12 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
 #pragma unroll
         for (int o = 1; o < P; o <<= 1) smax = max(smax, __shfl_xor(smax, o, kWave));
         if (gact) {
-            if (!REV && smax > kPackedMaxScore) {
+            if (P == kWave && !F16 && smax > kPackedMaxScore) {
                 // some value may not fit 16 bits: the pair continues in int32
                 // from this super-strip, whose input row (every value of the
-                // super-strips above is exact) stays in buffer bi
+                // super-strips above is exact) stays in buffer bi.  (Only a
+                // whole wave gets pairs long enough; half-precision passes
+                // run only under kF16MaxScore.)
                 pick.s = -1;
                 pick.ss = ss;
                 pick.buf = bi;
@@ -1316,7 +1318,6 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
                 sw_result bad;
                 bad.score = bad.q_start = bad.q_end = bad.r_start = bad.r_end = -1;
                 a.out[pid] = bad;
-                if (a.phase == 1) a.pair_cell[pid] = -1;  // no start pass
             }
             pid = -1;
             m = n = 0;
@@ -1327,9 +1328,7 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     uint4* xbuf = reinterpret_cast<uint4*>(lds + kNumCodes * kWave * prof_bytes(R));
     // forward pass done: phase 1 stores score and end, the start pass follows
     // in phase 0
-    // in phase 0.  Phase 1 also sorts the pair for its start pass: the cell of
-    // the region q[0..end] x r[0..end] (none at score 0) into pair_cell and
-    // the start passes' histogram, so that their launch needs no classify.
+    // in phase 0
     auto forward_done = [&](int packed_s) __attribute__((always_inline)) {
         if (pid >= 0 && u == 0 && packed_s >= 0 && f.s != packed_s)
             atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
@@ -1340,9 +1339,6 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
             r.q_end = f.s > 0 ? f.i : -1;
             r.r_end = f.s > 0 ? f.j : -1;
             a.out[pid] = r;
-            const int cell = f.s > 0 && f.i >= 0 && f.j >= 0 ? cell_of(a, (int64_t)f.i + 1, (int64_t)f.j + 1) : -1;
-            a.pair_cell[pid] = cell;
-            if (cell >= 0) atomicAdd(&a.cell_count_next[cell * kCellShards + pid % kCellShards], 1);
         }
     };
     // packed score passes for every pair up to kMaxP16Len residues (the one-,
@@ -1439,26 +1435,42 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
         const int64_t qr = qoff + (hs ? f.i : 0), rr = roff + (hs ? f.j : 0);
         const int mr = hs ? f.i + 1 : 0, nr = hs ? f.j + 1 : 0;
         Best r{0, -1, -1};
-        // Every value of the start pass is at most the score, so when the
-        // score (plus the 15 of a biased substitution score) fits 16 bits
-        // the pass runs in packed cells, and its recompute in narrow
-        // cells whose 16-bit column tags cover the region's columns.
-        bool packed_start = false;
-        if constexpr (R == 16) packed_start = uni(f.s) <= kPackedMaxScore && uni(nr) <= kNarrowMaxCols;
-        if (packed_start) {
-            uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
-            if (uni(f.s) <= kF16MaxScore) {
-                const StripPick pr = packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
-                packed_sweep<P, true, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
-                                                  pr.buf, &r);
-            } else {
-                const StripPick pr = packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
-                packed_sweep<P, true, false, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
-                                                   pr.buf, &r);
+        // Every value of the start pass is at most the score.  The pass runs
+        // in packed cells (half-precision maxima when the score is at most
+        // kF16MaxScore) and its recompute in narrow cells whose 16-bit column
+        // tags cover the region's columns; a score above kPackedMaxScore
+        // makes the packed pass stop at the first super-strip whose values
+        // pass 16 bits, and the int32 scan goes on from there.
+        const bool scan_fits_r = 3 * wide_buf_words(nr) <= a.slot_words;
+        bool start_done = false;
+        int ss0 = 0, buf0 = 0;  // where an int32 scan starts
+        if constexpr (R == 16) {
+            if (uni(nr) <= kNarrowMaxCols) {
+                uint32_t* xw = reinterpret_cast<uint32_t*>(xbuf);
+                if (uni(f.s) <= kF16MaxScore) {
+                    const StripPick pr = packed_sweep<P, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+                    packed_sweep<P, true, true, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
+                                                      pr.buf, &r);
+                    start_done = true;
+                } else {
+                    const StripPick pr = packed_sweep<P, true, false>(a, prof, xw, slot, qr, mr, rr, nr, f.s);
+                    if (uni(pr.s) >= 0) {
+                        packed_sweep<P, true, false, true>(a, prof, xw, slot, qr, mr, rr, nr, f.s,
+                                                           hs ? pr.ss : -1, pr.buf, &r);
+                        start_done = true;
+                    } else if (scan_fits_r && uni(pr.ss) > 0) {
+                        // the super-strips above pr.ss stayed below the score
+                        ss0 = uni(pr.ss);
+                        buf0 = widen_row(slot, uni(pr.buf), nr);
+                    }
+                }
             }
-        } else if (scan_fits) {
+        }
+        if (start_done) {
+        } else if (scan_fits_r) {
             StripPick pr{0, -1, 0};
-            group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr);
+            group_sweep<R, P, true, true, false, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, -1, 0, &pr, ss0,
+                                                       buf0);
             r = group_sweep<R, P, true, true, true>(a, prof, xbuf, slot, qr, mr, rr, nr, f.s, hs ? pr.ss : -1,
                                                     pr.buf);
         } else {
@@ -1584,6 +1596,16 @@ __global__ void k_pack(const uint8_t* __restrict__ ascii, int64_t n, uint32_t* _
 }
 
 // ------------------------------------------------------------------ counting sort into cells
+// Start-pass cell of a pair whose forward pass is done: by the reversed
+// prefixes q[0..q_end], r[0..r_end]; -1 when there is nothing to do (score 0,
+// or a pair the forward pass rejected).
+__device__ __forceinline__ int classify_start(const Args& a, int64_t k)
+{
+    const sw_result r = a.out[k];
+    if (r.score <= 0 || r.q_end < 0 || r.r_end < 0) return -1;
+    return cell_of(a, (int64_t)r.q_end + 1, (int64_t)r.r_end + 1);
+}
+
 __device__ __forceinline__ int classify(const Args& a, int64_t k)
 {
     const int64_t qi = a.pairs[2 * k], ri = a.pairs[2 * k + 1];
@@ -1618,10 +1640,8 @@ __global__ void k_fill(int32_t* p, int64_t n, int32_t v)
 
 __global__ void k_zero_cells(Args a)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNumCells * kCellShards; i += gridDim.x * blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kNumCells * kCellShards; i += gridDim.x * blockDim.x)
         a.cell_count[i] = 0;
-        a.cell_count_next[i] = 0;
-    }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntHead] = 0;
 }
 
@@ -1629,7 +1649,7 @@ __global__ void k_prepare(Args a)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int cell = classify(a, k);
+        const int cell = a.phase == 2 ? classify_start(a, k) : classify(a, k);
         a.pair_cell[k] = cell;
         if (cell >= 0) atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1);
         else if (cell == -2) atomicOr((unsigned*)a.err, (unsigned)kErrRange);
@@ -1841,10 +1861,8 @@ hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err,
 hipError_t launch_prepare(const Args& a, hipStream_t stream)
 {
     const int64_t blocks = std::min<int64_t>((a.n_pairs + 255) / 256, 4096);
-    if (a.phase != 2) {
-        hipLaunchKernelGGL(k_zero_cells, dim3(64), dim3(256), 0, stream, a);
-        hipLaunchKernelGGL(k_prepare, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
-    }
+    hipLaunchKernelGGL(k_zero_cells, dim3(64), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_scan_tiles, dim3(kScanTiles), dim3(kScanThreads), 0, stream, a);
     hipLaunchKernelGGL(k_scan_apply, dim3(kScanTiles), dim3(kScanThreads), 0, stream, a);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);

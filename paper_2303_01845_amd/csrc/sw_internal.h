@@ -93,7 +93,6 @@ struct Args {
     int32_t* pair_cell;        // [n_pairs] work cell of each pair (-1 none, -2 invalid)
     int32_t* perm;             // [n_pairs] pair indices sorted by rank of their cell
     int32_t* cell_count;       // [kNumCells][kCellShards] histogram, then scatter cursors
-    int32_t* cell_count_next;  // the start passes' histogram, counted by the forward launch
     const int32_t* rank_cell;  // [kNumCells] cell at each rank
     int32_t* rank_start;       // [kNumCells + 1] first perm position of each rank
     int32_t* counters;         // [kNumCounters]
@@ -127,9 +126,7 @@ __host__ __device__ inline int bucket_group_kind(int bucket, int override_kind, 
 
 // launchers (sw_device.hip); all asynchronous on `stream`
 hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err, hipStream_t stream);
-// zero, classify, scan, scatter; for phase 2 (start passes) only scan and
-// scatter: the forward launch classified its pairs into cell_count_next
-hipError_t launch_prepare(const Args& a, hipStream_t stream);
+hipError_t launch_prepare(const Args& a, hipStream_t stream);  // zero, classify, scan, scatter
 hipError_t launch_persistent(const Args& a, int grid, hipStream_t stream);
 hipError_t launch_plain(const Args& a, int kind, int first, int count, int grid, hipStream_t stream);
 hipError_t set_kernel_attributes();
