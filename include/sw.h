@@ -170,7 +170,7 @@ SW_API int sw_workspace_size(int64_t n_pairs, int64_t max_len, size_t* bytes);
  * 256-byte aligned, workspace_bytes long, owned by the caller; the library
  * allocates no device memory for the call and keeps no pointer into the
  * buffer after the enqueued work completes).  The buffer holds the sort
- * tables, the two pair arrays and then as many boundary-row slots of at
+ * tables, the three pair arrays and then as many boundary-row slots of at
  * least 768 KiB as fit, up to one per resident block of the persistent grid:
  * a buffer below the sw_workspace_size figure runs a smaller grid (fewer
  * blocks at once, same results).  Two calls in flight at the same time must

@@ -183,6 +183,7 @@ struct DiscoverSpace {
 struct Workspace {
     int64_t pair_cap = 0;
     int32_t* pair_cell = nullptr;
+    int32_t* pair_rank = nullptr;
     int32_t* perm = nullptr;
     int32_t* cell_count = nullptr;
     int32_t* rank_start = nullptr;
@@ -233,6 +234,7 @@ struct Workspace {
             (void)hipEventDestroy(e.second);
         }
         (void)hipFree(pair_cell);
+        (void)hipFree(pair_rank);
         (void)hipFree(perm);
         (void)hipFree(cell_count);
         (void)hipFree(rank_start);
@@ -358,6 +360,7 @@ int get_workspace(Device& d, hipStream_t stream, Workspace** out)
 // own per-stream arrays, or one buffer the caller owns, carved the same way.
 struct WsView {
     int32_t* pair_cell = nullptr;
+    int32_t* pair_rank = nullptr;
     int32_t* perm = nullptr;
     int32_t* cell_count = nullptr;
     int32_t* rank_start = nullptr;
@@ -376,11 +379,11 @@ size_t ws_head_bytes(int64_t n_pairs)
 {
     const size_t np = (size_t)std::max<int64_t>(n_pairs, 1);
     return up_ws(sizeof(int32_t) * kNumCells * kCellShards) + up_ws(sizeof(int32_t) * (kNumCells + 1)) +
-           up_ws(sizeof(int32_t) * kNumCounters) + 2 * up_ws(sizeof(int32_t) * np);
+           up_ws(sizeof(int32_t) * kNumCounters) + 3 * up_ws(sizeof(int32_t) * np);
 }
 
 // Lay one call's arrays out in a buffer of `bytes`: the sort tables and the
-// two pair arrays, then as many boundary-row slots of at least slot_words()
+// three pair arrays, then as many boundary-row slots of at least slot_words()
 // as fit, up to max_grid (one per resident block of the persistent grid);
 // the slots share what is left, up to the size at which every pair takes the
 // whole-wave scan.  SW_ENOMEM if not even one slot fits.
@@ -404,6 +407,7 @@ int carve_workspace(void* base, size_t bytes, int64_t n_pairs, int max_grid, WsV
     v->rank_start = take(sizeof(int32_t) * (kNumCells + 1));
     v->counters = take(sizeof(int32_t) * kNumCounters);
     v->pair_cell = take(sizeof(int32_t) * np);
+    v->pair_rank = take(sizeof(int32_t) * np);
     v->perm = take(sizeof(int32_t) * np);
     v->scratch = reinterpret_cast<uint32_t*>(p);
     v->slot_words = sw;
@@ -427,7 +431,8 @@ int library_workspace(Workspace& w, int64_t n_pairs, int grid, WsView* v)
     if (n_pairs > w.pair_cap) {
         const int64_t cap = std::max<int64_t>(n_pairs, 2 * w.pair_cap);
         int rc;
-        if ((rc = grow(&w.pair_cell, cap)) || (rc = grow(&w.perm, cap))) return rc;
+        if ((rc = grow(&w.pair_cell, cap)) || (rc = grow(&w.pair_rank, cap)) || (rc = grow(&w.perm, cap)))
+            return rc;
         w.pair_cap = cap;
         changed = true;
     }
@@ -443,6 +448,7 @@ int library_workspace(Workspace& w, int64_t n_pairs, int grid, WsView* v)
     }
     if (changed) w.drop_graphs();
     v->pair_cell = w.pair_cell;
+    v->pair_rank = w.pair_rank;
     v->perm = w.perm;
     v->cell_count = w.cell_count;
     v->rank_start = w.rank_start;
@@ -678,6 +684,7 @@ void fill_args(Args& a, const Device& d, const WsView& v, const void* q_packed_d
     a.n_pairs = n_pairs;
     a.out = out_dev;
     a.pair_cell = v.pair_cell;
+    a.pair_rank = v.pair_rank;
     a.perm = v.perm;
     a.cell_count = v.cell_count;
     a.rank_start = v.rank_start;

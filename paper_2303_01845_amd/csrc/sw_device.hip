@@ -1645,19 +1645,21 @@ __global__ void k_zero_cells(Args a)
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntHead] = 0;
 }
 
+// Classify each pair into its cell and reserve its place: a returning atomic
+// on the cell's shard gives its rank there.
 __global__ void k_prepare(Args a)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int cell = a.phase == 2 ? classify_start(a, k) : classify(a, k);
         a.pair_cell[k] = cell;
-        if (cell >= 0) atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1);
+        if (cell >= 0) a.pair_rank[k] = atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1);
         else if (cell == -2) atomicOr((unsigned*)a.err, (unsigned)kErrRange);
     }
 }
 
 // Exclusive scan of the cell counts in rank order (a cell's shards in shard
-// order): the counts become scatter cursors, rank_start gets the first
+// order): the counts become first positions, rank_start gets the first
 // position of each rank, counters the number of pairs of each kind.  Two
 // launches of kScanTiles blocks: each block sums its tile of kScanRanks
 // ranks (all pairs, and those of 64-, 16- and 8-lane items), then each block
@@ -1774,12 +1776,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(Args a)
     }
 }
 
+// Each pair to the place its classify reserved: the first position of its
+// cell and shard (from the scan) plus its rank there.
 __global__ void k_scatter(Args a)
 {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int cell = a.pair_cell[k];
-        if (cell >= 0) a.perm[atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1)] = (int32_t)k;
+        if (cell >= 0) a.perm[a.cell_count[cell * kCellShards + (int)(k % kCellShards)] + a.pair_rank[k]] = (int32_t)k;
     }
 }
 

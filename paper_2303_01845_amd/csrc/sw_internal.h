@@ -91,8 +91,9 @@ struct Args {
     int64_t n_pairs;
     sw_result* out;
     int32_t* pair_cell;        // [n_pairs] work cell of each pair (-1 none, -2 invalid)
+    int32_t* pair_rank;        // [n_pairs] its place among the pairs of its cell and shard
     int32_t* perm;             // [n_pairs] pair indices sorted by rank of their cell
-    int32_t* cell_count;       // [kNumCells][kCellShards] histogram, then scatter cursors
+    int32_t* cell_count;       // [kNumCells][kCellShards] histogram, then first perm position
     const int32_t* rank_cell;  // [kNumCells] cell at each rank
     int32_t* rank_start;       // [kNumCells + 1] first perm position of each rank
     int32_t* counters;         // [kNumCounters]
