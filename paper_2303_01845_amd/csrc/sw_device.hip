@@ -882,6 +882,12 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
 #pragma unroll
         for (int k = 0; k < 8; ++k) botp[k] = 0;
         uint4 tn0 = make_uint4(0, 0, 0, 0), tn1 = make_uint4(0, 0, 0, 0);
+        // one lane per pair: the boundary row is loaded two chunks ahead.
+        // Iterations go in pairs: the first reads set tn and loads chunks
+        // c + 2 into tn and c + 3 into tr, the second reads set tq and then
+        // takes tr into tq (by then tr has had two iterations to arrive).
+        uint4 tq0 = make_uint4(0, 0, 0, 0), tq1 = make_uint4(0, 0, 0, 0);
+        uint4 tr0 = make_uint4(0, 0, 0, 0), tr1 = make_uint4(0, 0, 0, 0);
         uint32_t nw_n = 0, hw_n = 0;
         // One lane per pair: the reference comes through LDS.  Every 8 chunks
         // a lane loads the aligned 16-byte groups holding the next 72
@@ -937,7 +943,18 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             tn1 = in4[cc * in_stride + 1];
             if constexpr (P > 1) window8(rv, chunk_x(cn), nw_n, hw_n);
         };
+        auto fetch_q = [&](int cn) __attribute__((always_inline)) {
+            const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
+            tq0 = in4[cc * in_stride];
+            tq1 = in4[cc * in_stride + 1];
+        };
+        auto fetch_r = [&](int cn) __attribute__((always_inline)) {
+            const int cc = min(max(cn, 0), max(my_chunks - 1, 0));
+            tr0 = in4[cc * in_stride];
+            tr1 = in4[cc * in_stride + 1];
+        };
         fetch(-u);
+        if constexpr (P == 1) fetch_q(1);
         if constexpr (P == 1) {
             sn0 = b0n0;
             sn1 = b0n1;
@@ -959,12 +976,29 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         // B on 8c-1 .. 8c+6.  Each lane needs my_chunks + 1 chunk iterations
         // (the last one for B's final column); the very last iteration of the
         // wave has a single step.
-        auto iteration = [&](int t, auto steps_tag) __attribute__((always_inline)) {
+        // With one lane per pair, iteration t reads its row from set tn (t
+        // even) or tq (t odd).
+        auto iteration = [&](int t, auto steps_tag, auto set_tag) __attribute__((always_inline)) {
             constexpr int STEPS = decltype(steps_tag)::value;
+            constexpr bool SET_Q = P == 1 && decltype(set_tag)::value;
             const int c = t - u;
             const bool act = gact && c >= 0 && c <= my_chunks;
             const int tag0 = 0xFFFF - 8 * c;  // ONE: tag of column 8c (A); B is one column behind
-            uint32_t top[8] = {tn0.x, tn0.y, tn0.z, tn0.w, tn1.x, tn1.y, tn1.z, tn1.w};
+            uint32_t top[8];
+            if constexpr (SET_Q) {
+                top[0] = tq0.x, top[1] = tq0.y, top[2] = tq0.z, top[3] = tq0.w;
+                top[4] = tq1.x, top[5] = tq1.y, top[6] = tq1.z, top[7] = tq1.w;
+            } else {
+                top[0] = tn0.x, top[1] = tn0.y, top[2] = tn0.z, top[3] = tn0.w;
+                top[4] = tn1.x, top[5] = tn1.y, top[6] = tn1.z, top[7] = tn1.w;
+            }
+            if constexpr (P == 1) {
+                // copies of their own, so that the set's registers take the
+                // next load at once and keep them across the loop
+#pragma unroll
+                for (int k = 0; k < 8; ++k) opaque(top[k]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
             if constexpr (P > 1) {
                 // both sources are read and the values selected (a select of
                 // addresses would turn into flat loads)
@@ -990,7 +1024,16 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 }
                 window_lds(c + 1);
             }
-            if (t + 1 <= wc + P - 1) fetch(c + 1);
+            if constexpr (P == 1) {
+                // unconditional (the index is clamped), so that each set
+                // keeps its registers from one pair of iterations to the next
+                if constexpr (!SET_Q) {
+                    fetch(c + 2);
+                    fetch_r(c + 3);
+                }
+            } else if (t + 1 <= wc + P - 1) {
+                fetch(c + 1);
+            }
             // B's row 15 per step.  An idle lane hands zeros to lane u + 1;
             // with one lane per pair the values are only read after an
             // active iteration, so nothing is cleared.
@@ -1117,11 +1160,36 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) botp[k] = bq[k];
+            if constexpr (SET_Q) {
+                tq0 = tr0;
+                tq1 = tr1;
+            }
         };
         const int T = wc + P;  // iterations 0 .. wc + P - 1
+        using Full = std::integral_constant<int, 8>;
+        using Last = std::integral_constant<int, 1>;
+        using SetN = std::integral_constant<bool, false>;
+        using SetQ = std::integral_constant<bool, true>;
+        if constexpr (P == 1) {
+            // iterations in pairs (sets tn, tq), then what is left: the
+            // last full one (set tn) if T is even, and the last (one step)
+            int t = 0;
 #pragma unroll 1
-        for (int t = 0; t < T - 1; ++t) iteration(t, std::integral_constant<int, 8>());
-        iteration(T - 1, std::integral_constant<int, 1>());
+            for (; t + 1 < T - 1; t += 2) {
+                iteration(t, Full(), SetN());
+                iteration(t + 1, Full(), SetQ());
+            }
+            if (t < T - 1) {
+                iteration(t, Full(), SetN());
+                iteration(T - 1, Last(), SetQ());
+            } else {
+                iteration(T - 1, Last(), SetN());
+            }
+        } else {
+#pragma unroll 1
+            for (int t = 0; t < T - 1; ++t) iteration(t, Full(), SetN());
+            iteration(T - 1, Last(), SetN());
+        }
         block_fence();
         if constexpr (ONE) {
             // the lane's first row with a cell at the target, then the
