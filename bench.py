@@ -359,8 +359,11 @@ def c3_shard_bench(sw, torch, args):
         "gcups_fwd": round(cells / (fwd_ms * 1e-3) / 1e9, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
-                     "peak_basis": "int32 VALU: %.1f%% of the cells are in pairs over 4,096 residues, "
-                                   "aligned by the int32 whole-wave path" % (100 * wide)},
+                     "peak_basis": "int32 VALU: %.1f%% of the cells are in pairs over 4,096 residues, whose "
+                                   "passes run in packed 16-bit cells up to the first super-strip where a "
+                                   "value passes 16 bits and in int32 from there; against the packed 16-bit "
+                                   "peak %.2f TOP/s the fraction is %.4f" % (
+                                       100 * wide, PEAK_PACKED16_TOPS, achieved / PEAK_PACKED16_TOPS)},
         "projected_full_set_s": round(call_ms * 1e-3 * float(load.max()) / float(load[0]), 2),
         "projected_note": "the whole 10M-pair set on %d GPUs: the largest shard's cost at this shard's rate "
                           "(no transfer or collective time)" % G,
