@@ -439,7 +439,8 @@ def search_bench(sw, torch, ps, packed_d, offs_d, stream, args, res, align_ms, c
     """The whole search on the device (sw_search): discovery of the block
     workload's candidates, their alignment and the identity / coverage filter,
     with the queries in 1, 2 and 4 blocks (with more than one, the next
-    block's discovery and alignment overlap the current block's filter).
+    block's discovery overlaps the current block, and consecutive blocks run
+    on two streams).
     Wall time per call (the call is synchronous), beside the sum of the three
     stages timed alone; the edge count is checked against the stage calls'."""
     nq = (ps.n_seqs + 1) // 2
@@ -467,9 +468,9 @@ def search_bench(sw, torch, ps, packed_d, offs_d, stream, args, res, align_ms, c
     best = min(runs, key=lambda k: runs[k]["ms"])
     return {"ms": runs[best]["ms"], "blocks": int(best), "by_blocks": runs,
             "candidates": st["candidates"], "edges": st["edges"], "stages_sum_ms": round(stage_ms, 3),
-            "stages": "sw_search: sw_discover per query block on one stream, sw_align_sets on a second, "
-                      "sw_identity + edge compaction on a third; stages_sum_ms adds the three stages timed "
-                      "alone (the alignment including packing)",
+            "stages": "sw_search: sw_discover per query block on one stream, then each block's sw_align_sets, "
+                      "sw_identity and edge compaction on one of two more, alternately; stages_sum_ms adds the "
+                      "three stages timed alone (the alignment including packing)",
             "steps": steps}
 
 

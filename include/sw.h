@@ -443,12 +443,17 @@ SW_API int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, i
  * to the outputs: edges_dev int32[2 * edge_cap] (query, reference),
  * edge_results_dev sw_result[edge_cap], edge_ident_dev
  * sw_identity_result[edge_cap], in no particular order (the set is exact).
- * Discovery, alignment and the filter run on three internal streams, so the
- * discovery of block b+1 overlaps the alignment of block b and the
- * alignment of block b+1 the filter of block b; two sets of block buffers,
- * kept by the library and grown to the largest block, bound the memory.  The
- * streams start after the work already enqueued on `stream`; the call
- * returns when everything is done.
+ * Discovery runs on `stream` (after the work already enqueued on it); each
+ * block's alignment and filter run on one of two internal streams,
+ * alternately, so the discovery of block b+1 overlaps the alignment of
+ * block b and block b+1's launches fill the compute units that block b's
+ * last long items leave idle; two sets of block buffers, kept by the
+ * library and grown to the largest block, bound the memory.  The call
+ * returns when everything is done.  HIP maps streams onto GPU_MAX_HW_QUEUES
+ * hardware queues (4 by default) and two streams on one queue run one after
+ * the other: with more streams alive in the process (the library's graph
+ * capture stream, server slots, the caller's own) the two internal streams
+ * may share a queue, and the blocks then no longer overlap.
  * *stats receives the candidates, the edges (all of them, also when more
  * than edge_cap: then only edge_cap are written and the call returns
  * SW_ENOMEM) and the number of blocks.  Calls on one device run one at a

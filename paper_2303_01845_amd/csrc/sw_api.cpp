@@ -267,8 +267,8 @@ struct Device {
     hipStream_t capture_stream = nullptr;     // created by the first graph capture
     // sw_search: its discovery, alignment and filter streams, events and the
     // two sets of per-block buffers (kept, grown to the largest block)
-    hipStream_t search_stream[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t search_ev[7] = {};  // start, then per buffer set: discovered, aligned, filtered
+    hipStream_t search_stream[2] = {nullptr, nullptr};  // alignment and filter, per buffer set
+    hipEvent_t search_ev[4] = {};  // per buffer set: discovered (0, 1), filtered (2, 3)
     int64_t search_cap = 0;
     int32_t* search_pairs[2] = {nullptr, nullptr};
     sw_result* search_res[2] = {nullptr, nullptr};
@@ -1185,7 +1185,7 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
     DiscoverSpace* xp = nullptr;
     DiscoverPrep prep;
     std::vector<uint64_t> qp;
-    hipStream_t sd = nullptr, sa = nullptr, si = nullptr;
+    hipStream_t sd = nullptr, sa[2] = {nullptr, nullptr};
     {
         std::lock_guard<std::mutex> lock(g_mutex);
         if ((rc = get_device(&dp))) return rc;
@@ -1198,15 +1198,15 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
             if ((rc = grow(&d.search_count, 1))) return rc;
             HIP_TRY(hipHostMalloc((void**)&d.search_count_host, sizeof(unsigned long long)), "hipHostMalloc");
         }
-        sd = d.search_stream[0];
-        sa = d.search_stream[1];
-        si = d.search_stream[2];
-        // the three streams start after the caller's earlier work
-        HIP_TRY(hipEventRecord(d.search_ev[0], caller), "hipEventRecord");
-        HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[0], 0), "hipStreamWaitEvent");
-        HIP_TRY(hipStreamWaitEvent(sa, d.search_ev[0], 0), "hipStreamWaitEvent");
-        HIP_TRY(hipStreamWaitEvent(si, d.search_ev[0], 0), "hipStreamWaitEvent");
-        HIP_TRY(hipMemsetAsync(d.search_count, 0, sizeof(unsigned long long), si), "clear counter");
+        // discovery on the caller's stream (after its earlier work), the
+        // blocks' alignment and filter on two streams of the library's, after
+        // events of it.  (HIP spreads streams over a few hardware queues,
+        // GPU_MAX_HW_QUEUES, 4 by default; two streams on one queue run one
+        // after the other, so the call adds no more streams than it needs.)
+        sd = caller;
+        sa[0] = d.search_stream[0];
+        sa[1] = d.search_stream[1];
+        HIP_TRY(hipMemsetAsync(d.search_count, 0, sizeof(unsigned long long), sd), "clear counter");
         if ((rc = discover_prepare(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r, k, sd, &xp,
                                    &prep)))
             return rc;
@@ -1240,7 +1240,7 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
         {
             std::lock_guard<std::mutex> lock(g_mutex);
             // the block two back must have released this buffer set
-            if (b >= 2) HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[5 + buf], 0), "hipStreamWaitEvent");
+            if (b >= 2) HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[2 + buf], 0), "hipStreamWaitEvent");
             HIP_TRY(hipMemsetAsync(x.counters + kKmOut, 0, sizeof(uint64_t), sd), "clear counter");
             if ((rc = discover_join(x, prep, mode, min_shared, ranges[b], d.search_pairs[buf], nullptr, need, sd)))
                 return rc;
@@ -1250,44 +1250,42 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
                 std::snprintf(g_last_error, sizeof(g_last_error), "sw_search: a block found more pairs than matches");
                 return SW_EDEVICE;
             }
-            HIP_TRY(hipEventRecord(d.search_ev[1 + buf], sd), "hipEventRecord");
-            HIP_TRY(hipStreamWaitEvent(sa, d.search_ev[1 + buf], 0), "hipStreamWaitEvent");
+            HIP_TRY(hipEventRecord(d.search_ev[buf], sd), "hipEventRecord");
+            HIP_TRY(hipStreamWaitEvent(sa[buf], d.search_ev[buf], 0), "hipStreamWaitEvent");
         }
         candidates += n_b;
-        // the block's alignment on the alignment stream, then its filter and
-        // edge compaction on the filter stream: the next block's discovery
-        // and alignment are enqueued meanwhile, so they can take the compute
-        // units the filter's last long boxes leave free
+        // the block's alignment, filter and edge compaction on the stream of
+        // its buffer set: consecutive blocks run on different streams, so the
+        // next block's launches take the compute units that this block's
+        // last long items leave idle, and the discovery of the block after
+        // runs meanwhile on its own stream
         if (n_b > 0) {
             if ((rc = align_impl(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r,
-                                 d.search_pairs[buf], n_b, scoring, d.search_res[buf], WsMode::library, nullptr, 0, sa,
-                                 SW_NO_GRAPH)))
+                                 d.search_pairs[buf], n_b, scoring, d.search_res[buf], WsMode::library, nullptr, 0,
+                                 sa[buf], SW_NO_GRAPH)))
                 return rc;
-        }
-        HIP_TRY(hipEventRecord(d.search_ev[3 + buf], sa), "hipEventRecord");
-        HIP_TRY(hipStreamWaitEvent(si, d.search_ev[3 + buf], 0), "hipStreamWaitEvent");
-        if (n_b > 0) {
             if ((rc = sw_identity(q_packed_dev, q_offsets_dev, n_q, r_packed_dev, r_offsets_dev, n_r,
                                   d.search_pairs[buf], n_b, scoring, d.search_res[buf], ani_permille, cov_permille,
-                                  d.search_id[buf], si, 0)))
+                                  d.search_id[buf], sa[buf], 0)))
                 return rc;
             HIP_TRY(launch_edges(d.search_pairs[buf], d.search_res[buf], d.search_id[buf], n_b, edges_dev,
-                                 edge_results_dev, edge_ident_dev, edge_cap, d.search_count, si),
+                                 edge_results_dev, edge_ident_dev, edge_cap, d.search_count, sa[buf]),
                     "edges launch");
         }
-        HIP_TRY(hipEventRecord(d.search_ev[5 + buf], si), "hipEventRecord");
+        HIP_TRY(hipEventRecord(d.search_ev[2 + buf], sa[buf]), "hipEventRecord");
     }
-    HIP_TRY(hipMemcpyAsync(d.search_count_host, d.search_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, si),
+    // the count once both streams are done
+    HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[2], 0), "hipStreamWaitEvent");
+    HIP_TRY(hipStreamWaitEvent(sd, d.search_ev[3], 0), "hipStreamWaitEvent");
+    HIP_TRY(hipMemcpyAsync(d.search_count_host, d.search_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, sd),
             "read counter");
-    HIP_TRY(hipStreamSynchronize(si), "hipStreamSynchronize");
-    HIP_TRY(hipStreamSynchronize(sa), "hipStreamSynchronize");
     HIP_TRY(hipStreamSynchronize(sd), "hipStreamSynchronize");
     stats->candidates = candidates;
     stats->edges = (int64_t)*d.search_count_host;
     stats->blocks = (int32_t)ranges.size();
     {
         std::lock_guard<std::mutex> lock(g_mutex);
-        if ((rc = read_and_clear_errors(d, si))) return rc;
+        if ((rc = read_and_clear_errors(d, sd))) return rc;
     }
     return stats->edges > edge_cap ? SW_ENOMEM : SW_OK;
 }
