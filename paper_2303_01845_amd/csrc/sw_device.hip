@@ -1268,11 +1268,8 @@ __device__ __forceinline__ int cell_kind(int cell, const Args& a)
     return bucket_group_kind(bucket, a.bucket_kind[bucket], a.group8_max_len, a.group16_max_len);
 }
 
-// Cell of a pair: lane-per-pair pairs by (strips, chunks), long pairs by
-// (length bucket, 16*log2(m*n)).  Returns -1 for pairs that need no work and
-// -2 for invalid pairs (their result is written here).
-// Cell of a pair of lengths m, n > 0 (lane-per-pair cells by (strips,
-// chunks), longer pairs by (length bucket, 16*log2(m*n))).
+// Cell of a pair of lengths m, n > 0: lane-per-pair pairs by (strips,
+// chunks), longer pairs by (length bucket, 16*log2(m*n)).
 __device__ __forceinline__ int cell_of(const Args& a, int64_t m, int64_t n)
 {
     const int64_t mx = m > n ? m : n;
@@ -1674,6 +1671,8 @@ __device__ __forceinline__ int classify_start(const Args& a, int64_t k)
     return cell_of(a, (int64_t)r.q_end + 1, (int64_t)r.r_end + 1);
 }
 
+// Cell of pair k for its forward pass; -1 for pairs that need no work and -2
+// for invalid pairs (the result of both is written here).
 __device__ __forceinline__ int classify(const Args& a, int64_t k)
 {
     const int64_t qi = a.pairs[2 * k], ri = a.pairs[2 * k + 1];
