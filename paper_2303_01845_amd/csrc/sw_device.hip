@@ -1712,16 +1712,49 @@ __global__ void k_zero_cells(Args a)
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counters[kCntHead] = 0;
 }
 
-// Classify each pair into its cell and reserve its place: a returning atomic
-// on the cell's shard gives its rank there.
-__global__ void k_prepare(Args a)
+// Classify each pair into its cell and reserve its place.  A block takes a
+// tile of kPrepTile pairs: their counts per cell in LDS (an LDS atomic gives
+// each pair its rank among the tile's pairs of its cell), then one global
+// atomic per cell the tile holds reserves the tile's range on the cell's
+// shard (the tile index mod kCellShards).  The global atomics, about 7 G/s
+// one per pair, were the cost of this kernel.
+constexpr int kPrepThreads = 1024;
+constexpr int kPrepPer = 8;  // pairs per thread
+constexpr int kPrepTile = kPrepThreads * kPrepPer;
+__device__ __forceinline__ int pair_shard(int64_t k) { return (int)((k / kPrepTile) % kCellShards); }
+
+__global__ __launch_bounds__(kPrepThreads) void k_prepare(Args a)
 {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int cell = a.phase == 2 ? classify_start(a, k) : classify(a, k);
-        a.pair_cell[k] = cell;
-        if (cell >= 0) a.pair_rank[k] = atomicAdd(&a.cell_count[cell * kCellShards + (int)(k % kCellShards)], 1);
-        else if (cell == -2) atomicOr((unsigned*)a.err, (unsigned)kErrRange);
+    __shared__ int hist[kNumCells];  // the tile's count of each cell, then its first rank on the shard
+    for (int i = threadIdx.x; i < kNumCells; i += kPrepThreads) hist[i] = 0;
+    __syncthreads();
+    const int64_t k0 = (int64_t)blockIdx.x * kPrepTile + threadIdx.x;
+    int cells[kPrepPer], local[kPrepPer];
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < kPrepPer; ++i) {
+        const int64_t k = k0 + (int64_t)i * kPrepThreads;
+        int cell = -1;
+        if (k < a.n_pairs) {
+            cell = a.phase == 2 ? classify_start(a, k) : classify(a, k);
+            a.pair_cell[k] = cell;
+            bad = bad || cell == -2;
+        }
+        cells[i] = cell;
+        local[i] = cell >= 0 ? atomicAdd(&hist[cell], 1) : 0;
+    }
+    if (bad) atomicOr((unsigned*)a.err, (unsigned)kErrRange);
+    __syncthreads();
+    const int shard = (int)(blockIdx.x % kCellShards);
+    for (int c = threadIdx.x; c < kNumCells; c += kPrepThreads) {
+        const int cnt = hist[c];
+        if (cnt > 0) hist[c] = atomicAdd(&a.cell_count[c * kCellShards + shard], cnt);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPrepPer; ++i) {
+        const int64_t k = k0 + (int64_t)i * kPrepThreads;
+        if (cells[i] >= 0) a.pair_rank[k] = hist[cells[i]] + local[i];
     }
 }
 
@@ -1850,7 +1883,7 @@ __global__ void k_scatter(Args a)
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pairs;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int cell = a.pair_cell[k];
-        if (cell >= 0) a.perm[a.cell_count[cell * kCellShards + (int)(k % kCellShards)] + a.pair_rank[k]] = (int32_t)k;
+        if (cell >= 0) a.perm[a.cell_count[cell * kCellShards + pair_shard(k)] + a.pair_rank[k]] = (int32_t)k;
     }
 }
 
@@ -1932,8 +1965,9 @@ hipError_t launch_pack(const char* ascii, int64_t n, void* packed, int32_t* err,
 hipError_t launch_prepare(const Args& a, hipStream_t stream)
 {
     const int64_t blocks = std::min<int64_t>((a.n_pairs + 255) / 256, 4096);
+    const int64_t tiles = (a.n_pairs + kPrepTile - 1) / kPrepTile;
     hipLaunchKernelGGL(k_zero_cells, dim3(64), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_prepare, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)std::max<int64_t>(tiles, 1)), dim3(kPrepThreads), 0, stream, a);
     hipLaunchKernelGGL(k_scan_tiles, dim3(kScanTiles), dim3(kScanThreads), 0, stream, a);
     hipLaunchKernelGGL(k_scan_apply, dim3(kScanTiles), dim3(kScanThreads), 0, stream, a);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, a);

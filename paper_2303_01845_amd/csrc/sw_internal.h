@@ -56,9 +56,9 @@ constexpr int kNumLenBuckets = 17;     // ceil(log2(max(m, n))), 0..16
 constexpr int kInterCells = kMaxInterStrips * kMaxInterChunks;
 constexpr int kWideCells = kNumLenBuckets * kWideCostBins;
 constexpr int kNumCells = kInterCells + kWideCells;
-// Each cell's count and scatter cursor is split over this many counters
-// (pair index mod kCellShards), so that the atomics of a popular cell do not
-// all land on one address.
+// Each cell's count is split over this many counters (by the classify
+// tile of the pair, mod kCellShards), so that the atomics of a popular cell
+// do not all land on one address.
 constexpr int kCellShards = 16;
 
 // The scan of the cell counts runs over tiles of kScanRanks ranks, one block
