@@ -64,3 +64,37 @@ def test_caller_workspace_matches_library_and_oracle(sw):
     with pytest.raises(sw.SwError) as e:
         sw.align_sets_ws(b.packed, b.offsets, b.packed, b.offsets, pairs, tiny)
     assert e.value.status == sw.SW_ENOMEM
+
+
+def test_small_slots_long_similar_pairs(sw):
+    """Pairs beyond 32,768 residues whose scores pass 16 bits, in a workspace
+    of least slots (768 KiB): three int32 boundary rows of such a pair do not
+    fit a slot, so after the packed pass stops (and for the start pass) they
+    run the in-place sweep; the results equal the library form (whose slots
+    take the int32 scan) and the oracle."""
+    import torch
+    rng = np.random.default_rng(33)
+    seqs = []
+    for L, rate in [(33400, 0.0), (33800, 0.02)]:
+        a = P.background(rng, L)
+        b = a.copy()
+        hit = rng.random(L) < rate
+        b[hit] = P.background(rng, int(hit.sum()))
+        seqs += [a, b]
+    Ls = np.array([len(x) for x in seqs], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(Ls)])
+    pairs = np.array([[0, 1], [1, 0], [2, 3], [3, 2]], dtype=np.int32)
+    ps = P.PairSet(np.concatenate(seqs), offs, pairs, "long similar")
+    exp = oracle.batch_ascii(ps.ascii, ps.offsets, ps.pairs, 11, 1)
+    assert (exp[:, 0] > 65504).all(), exp[:, 0]
+    say("long similar pairs: scores %s" % exp[:, 0].tolist())
+    b = sw.Batch(ps.ascii, ps.offsets)
+    pairs_d = torch.from_numpy(ps.pairs).cuda()
+    ref = sw.align_sets(b.packed, b.offsets, b.packed, b.offsets, pairs_d, flags=sw.VALIDATE).cpu().numpy()
+    assert (ref == exp).all(), (ref.tolist(), exp.tolist())
+    grid = torch.cuda.get_device_properties(0).multi_processor_count * sw.get_tuning()["blocks_per_cu"]
+    head = sw.workspace_size(ps.n_pairs, 0) - grid * SLOT_BYTES
+    ws = torch.empty(head + 2 * SLOT_BYTES, dtype=torch.uint8, device="cuda")
+    got = sw.align_sets_ws(b.packed, b.offsets, b.packed, b.offsets, pairs_d, ws, flags=sw.VALIDATE).cpu().numpy()
+    assert (got == exp).all(), (got.tolist(), exp.tolist())
+    say("long similar pairs: in-place sweeps in least slots equal the oracle")
