@@ -171,7 +171,7 @@ SW_API int sw_workspace_size(int64_t n_pairs, int64_t max_len, size_t* bytes);
  * allocates no device memory for the call and keeps no pointer into the
  * buffer after the enqueued work completes).  The buffer holds the sort
  * tables, the three pair arrays and then as many boundary-row slots of at
- * least 768 KiB as fit, up to one per resident block of the persistent grid:
+ * least 1,280 KiB as fit, up to one per resident block of the persistent grid:
  * a buffer below the sw_workspace_size figure runs a smaller grid (fewer
  * blocks at once, same results).  Two calls in flight at the same time must
  * not share a buffer.  Arguments, results and flags as for sw_align_sets.
@@ -188,7 +188,7 @@ SW_API int sw_align_sets_ws(const void* q_packed_dev, const int64_t* q_offsets_d
  * For callers that cannot allocate device memory (code under HIP-graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): sw_align_sets
  * with its device workspace in a fixed array that the library holds on every
- * device it is loaded on (256 MiB, kept until the process ends).  The call
+ * device it is loaded on (384 MiB, kept until the process ends).  The call
  * allocates nothing, host or device: it runs the persistent form without HIP
  * graphs and a smaller grid than sw_align_sets (as many blocks as boundary-row
  * slots fit the array), with the same results.  Every call on a device shares

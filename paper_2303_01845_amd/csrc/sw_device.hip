@@ -405,6 +405,10 @@ __host__ __device__ constexpr int64_t boundary_buf_words(int P)
     return (P == 1 ? (int64_t)kMaxInterChunks : (int64_t)(kMaxP16Len / 8)) * (kWave / P) * 8;
 }
 
+// Boundary buffer of a slot that holds a one-lane forward pass's kept rows
+// (after a ring of four); the slot takes kKeptBuf + 1 buffers of such groups.
+constexpr int kKeptBuf = 4;
+
 // The same for N columns: a whole wave also runs the start passes of longer
 // pairs in narrow cells (one group, one word per column, rounded to 256
 // bytes); three such buffers of 65,536 columns fill the least slot.
@@ -723,7 +727,8 @@ __device__ __forceinline__ Best group_sweep(const Args& a, uint8_t* prof, uint4*
 //
 // The pass keeps per row a running maximum only.  Forward: the pair's best
 // score and the first super-strip that reaches it, whose input boundary row is
-// kept by rotating three boundary buffers; REV: the first super-strip whose
+// kept by rotating three boundary buffers (one lane per pair: see RING below);
+// REV: the first super-strip whose
 // maximum reaches `target`, its input row still in the buffer it was read
 // from.  group_sweep<ONE> then recomputes that one super-strip in int32 with
 // cell trackers.
@@ -802,6 +807,17 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
     uint32_t* x_mid = xw + 8 * kWave + lane;
     const uint32_t* x_mid_up = xw + 8 * kWave + (lane > 0 ? lane - 1 : 0);
     int bi = 0, bo = 1, bk = 2;  // boundary buffers: input, output, kept (uniform in a group)
+    // One lane per pair: per-lane buffer choices would split each chunk's
+    // loads and stores over several buffers, so every lane takes the same
+    // ones, in turn: two for the start pass (a pass that stops writes nothing
+    // more), a ring of four for the forward pass, whose rows then live for
+    // three super-strips.  A lane's best row that outlives the next
+    // super-strip is copied during the one after (its source then neither
+    // read nor written) to region kKeptBuf, copy loads one chunk ahead.
+    constexpr bool RING = P == 1 && !REV && !ONE;
+    constexpr int kRingBufs = REV ? 2 : 4;
+    bool cp = false, cp_next = false;  // RING: copy row cp_src during this super-strip
+    int cp_src = 0;
     StripPick pick{0, -1, 0};
     auto chunk_x = [&](int c) __attribute__((always_inline)) -> int { return (c < 0 || 8 * c >= N) ? 0 : (REV ? -8 * c - 7 : 8 * c); };
 
@@ -868,7 +884,7 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         const bool read_top = sv > 0;
         const bool write_next = !ONE && ss + 1 < my_ss;
         // the first super-strip reads zeros (one 32-byte row for all chunks)
-        const int in_buf = ONE ? min(max(one_buf, 0), 2) : bi;
+        const int in_buf = ONE ? min(max(one_buf, 0), P == 1 ? kKeptBuf : 2) : bi;
         const uint4* in4 = read_top ? reinterpret_cast<const uint4*>(grp_slot + in_buf * BW) : g_zero_row;
         const int in_stride = read_top ? G * 2 : 0;
         uint4* out4 = reinterpret_cast<uint4*>(grp_slot + bo * BW);
@@ -889,6 +905,15 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
         uint4 tq0 = make_uint4(0, 0, 0, 0), tq1 = make_uint4(0, 0, 0, 0);
         uint4 tr0 = make_uint4(0, 0, 0, 0), tr1 = make_uint4(0, 0, 0, 0);
         uint32_t nw_n = 0, hw_n = 0;
+        // RING: the chunks of the copy in flight (even chunks in set n, odd
+        // in set q: a load never takes the registers a store just read), its
+        // source and destination
+        uint4 cn0 = make_uint4(0, 0, 0, 0), cn1 = make_uint4(0, 0, 0, 0);
+        uint4 cq0 = make_uint4(0, 0, 0, 0), cq1 = make_uint4(0, 0, 0, 0);
+        bool any_cp = false;
+        if constexpr (RING) any_cp = __ballot(cp) != 0;
+        const uint4* cp4 = reinterpret_cast<const uint4*>(grp_slot + (int64_t)cp_src * BW);
+        uint4* kept4 = reinterpret_cast<uint4*>(grp_slot + (int64_t)kKeptBuf * BW);
         // One lane per pair: the reference comes through LDS.  Every 8 chunks
         // a lane loads the aligned 16-byte groups holding the next 72
         // residues (3 of the nibble plane, 2 of the high plane) one batch
@@ -998,6 +1023,26 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
 #pragma unroll
                 for (int k = 0; k < 8; ++k) opaque(top[k]);
                 __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (RING) {
+                // the copy: chunk c - 1 (loaded one iteration ago, before
+                // that iteration's boundary loads, so waiting for it waits
+                // for nothing younger), then the load of chunk c
+                if (any_cp) {
+                    if (cp && c >= 1 && c - 1 < my_chunks) {
+                        kept4[(c - 1) * (G * 2)] = SET_Q ? cn0 : cq0;
+                        kept4[(c - 1) * (G * 2) + 1] = SET_Q ? cn1 : cq1;
+                    }
+                    if (cp && c < my_chunks) {
+                        if constexpr (SET_Q) {
+                            cq0 = cp4[c * (G * 2)];
+                            cq1 = cp4[c * (G * 2) + 1];
+                        } else {
+                            cn0 = cp4[c * (G * 2)];
+                            cn1 = cp4[c * (G * 2) + 1];
+                        }
+                    }
+                }
             }
             if constexpr (P > 1) {
                 // both sources are read and the values selected (a select of
@@ -1227,10 +1272,23 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                     pick.ss = ss;
                     pick.buf = bi;
                     done = true;
-                } else {
+                } else if (P > 1) {
                     const int tt = bi;
                     bi = bo;
                     bo = tt;
+                }
+            } else if (RING) {
+                if (smax > pick.s) {
+                    pick.s = smax;
+                    pick.ss = ss;
+                    pick.buf = bi;
+                } else {
+                    // the copy made during this super-strip now holds the
+                    // best row; a best row one super-strip old that the
+                    // ring would overwrite is copied during the next one
+                    if (cp) pick.buf = kKeptBuf;
+                    cp_next = pick.ss == ss - 1 && pick.ss > 0 && pick.ss + kRingBufs < my_ss;
+                    cp_src = pick.buf;
                 }
             } else if (smax > pick.s) {
                 pick.s = smax;
@@ -1245,6 +1303,14 @@ __device__ __forceinline__ StripPick packed_sweep(const Args& a, uint8_t* prof, 
                 bi = bo;
                 bo = tt;
             }
+        }
+        if constexpr (P == 1) {
+            // the same buffers on every lane, finished or not (a finished
+            // lane writes nothing, and a row it keeps is named by its pick)
+            bi = bo;
+            bo = bo + 1 == kRingBufs ? 0 : bo + 1;
+            cp = cp_next;
+            cp_next = false;
         }
     }
     return pick;
@@ -1372,12 +1438,14 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     }
     if (pid >= 0) {
         // the slot must hold one boundary cell per column for every group
-        // (narrow one-, 8- and 16-lane groups: three buffers of fixed size)
+        // (narrow groups: buffers of fixed size, five for one lane, three
+        // for 8 and 16)
         const int64_t need = (int64_t)((n + 7) / 8) * G * SW * 4;
         const bool may_pack = R == 16 && (P == 64 ? max(m, n) <= kMaxP16Len : !WIDE);
         const int max_chunks = P == 1 ? kMaxInterChunks : kMaxP16Len / 8;
         if (need > a.slot_words ||
-            (may_pack && ((n + 7) / 8 > max_chunks || 3 * boundary_buf_words(P) > a.slot_words))) {
+            (may_pack && ((n + 7) / 8 > max_chunks ||
+                          (P == 1 ? kKeptBuf + 1 : 3) * boundary_buf_words(P) > a.slot_words))) {
             if (u == 0) {
                 atomicOr((unsigned*)a.err, (unsigned)kErrInternal);
                 sw_result bad;
@@ -1455,7 +1523,8 @@ __device__ __forceinline__ void do_group(const Args& a, int first, int count, ui
     // as an int32 scan from the super-strip where it stopped (its input row
     // widened), keeping only each super-strip's maximum, then the exact cells
     // from one super-strip with trackers -- when three int32 boundary
-    // buffers of the pair fit the slot (pairs up to ~32k columns); else the
+    // buffers of the pair fit the slot (the least slot: pairs up to ~54k
+    // columns; the library's slots: every pair); else the
     // in-place sweep with trackers in every cell, from the top.  The start
     // pass the same way, packed when the score fits.
     if constexpr (WIDE) {
@@ -1900,10 +1969,11 @@ int64_t slot_words_for(int64_t max_len)
 int64_t slot_words()
 {
     // [chunk][group][8 cells]: 64 groups of one lane over at most 128 chunks
-    // (narrow, three buffers), 8 or 4 groups over 512 chunks (8 or 16 lanes,
-    // narrow), 1 group over 8192 chunks (64 lanes, wide, two words per cell;
-    // three buffers of the scan fit up to ~32k columns)
-    const int64_t p1 = 3 * boundary_buf_words(1);  // three boundary buffers of the packed pass
+    // (narrow, a ring of four buffers and the kept rows), 8 or 4 groups over
+    // 512 chunks (8 or 16 lanes, narrow, three buffers), 1 group over 8192
+    // chunks (64 lanes, wide, two words per cell; three buffers of the scan
+    // fit up to ~54k columns)
+    const int64_t p1 = (kKeptBuf + 1) * boundary_buf_words(1);
     const int64_t p8 = 3 * boundary_buf_words(8);
     const int64_t p16 = 3 * boundary_buf_words(16);
     const int64_t p64 = kWideBufWords;  // whole wave, longest pairs: one buffer, in place

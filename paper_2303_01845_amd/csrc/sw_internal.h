@@ -150,9 +150,9 @@ struct DeviceStatics {
     void* static_ws;  // kStaticWsBytes, the workspace of sw_align_sets_static
 };
 // The fixed workspace of the allocation-free entry point and the most pairs
-// one of its calls takes (their sort arrays, 32 MiB, leave room for 300
-// boundary-row slots of 768 KiB).
-constexpr size_t kStaticWsBytes = (size_t)256 << 20;
+// one of its calls takes (their sort arrays, 32 MiB, leave room for 281
+// boundary-row slots of 1,280 KiB).
+constexpr size_t kStaticWsBytes = (size_t)384 << 20;
 constexpr int64_t kStaticMaxPairs = (int64_t)1 << 22;
 hipError_t device_statics(DeviceStatics* out);
 void matrix_ncbi(int8_t out[kNumSym * kNumSym], char letters[kNumSym + 1]);

@@ -12,7 +12,7 @@ from workloads import proteins as P
 
 pytestmark = pytest.mark.gpu
 
-SLOT_BYTES = 196608 * 4  # the least boundary-row slot (768 KiB)
+SLOT_BYTES = 327680 * 4  # the least boundary-row slot (1,280 KiB)
 
 
 def say(msg):
@@ -67,15 +67,15 @@ def test_caller_workspace_matches_library_and_oracle(sw):
 
 
 def test_small_slots_long_similar_pairs(sw):
-    """Pairs beyond 32,768 residues whose scores pass 16 bits, in a workspace
-    of least slots (768 KiB): three int32 boundary rows of such a pair do not
-    fit a slot, so after the packed pass stops (and for the start pass) they
-    run the in-place sweep; the results equal the library form (whose slots
-    take the int32 scan) and the oracle."""
+    """Pairs beyond 54,600 residues whose scores pass 16 bits, in a workspace
+    of least slots (1,280 KiB): three int32 boundary rows of such a pair do
+    not fit a slot, so after the packed pass stops (and for the start pass)
+    they run the in-place sweep; the results equal the library form (whose
+    slots take the int32 scan) and the oracle."""
     import torch
     rng = np.random.default_rng(33)
     seqs = []
-    for L, rate in [(33400, 0.0), (33800, 0.02)]:
+    for L, rate in [(55000, 0.0), (56000, 0.02)]:
         a = P.background(rng, L)
         b = a.copy()
         hit = rng.random(L) < rate
