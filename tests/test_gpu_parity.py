@@ -268,6 +268,73 @@ def test_packed_overflow_long_pairs(sw):
     assert_same(gpu_align(sw, ps), exp, ps, "packed overflow")
 
 
+def planted_one_lane_set(seed):
+    """One-lane pairs (16 query rows per super-strip) whose best cell lies in a
+    chosen super-strip of the forward pass, at every distance from the pair's
+    last super-strip: a reference segment copied into the query so that the
+    copy ends in that super-strip; a weaker copy above or below a stronger
+    one (the best row moves down, or stays while later super-strips pass);
+    and exact ties (the reference is the segment itself, copied two or three
+    times into the query: the first copy's cell must be reported)."""
+    rng = np.random.default_rng(seed)
+    seqs = []
+
+    def plant(q, r, a, L, e):
+        q[e - L + 1:e + 1] = r[a:a + L]
+
+    for n_ss in range(1, 11):
+        for s in range(n_ss):
+            for variant in ("one", "higher_later", "lower_later", "tie"):
+                m = int(16 * n_ss - rng.integers(0, 16))
+                if s * 16 > m - 1:
+                    continue
+                e = int(rng.integers(16 * s, min(16 * s + 16, m)))
+                q = P.background(rng, m)
+                if variant == "tie":
+                    L = min(24, e + 1)
+                    r = P.background(rng, L)
+                    plant(q, r, 0, L, e)
+                    for s2 in range(s + 2, n_ss, 2):
+                        e2 = min(16 * s2 + int(rng.integers(0, 16)), m - 1)
+                        if e2 - L + 1 > e + 16:
+                            plant(q, r, 0, L, e2)
+                else:
+                    n = int(rng.integers(60, 1000))
+                    r = P.background(rng, n)
+                    L = min(24, e + 1, n)
+                    plant(q, r, int(rng.integers(0, n - L + 1)), L, e)
+                    d = int(rng.integers(1, 6))
+                    if variant != "one" and s + d < n_ss:
+                        e2 = min(16 * (s + d) + int(rng.integers(0, 16)), m - 1)
+                        L2 = 30 if variant == "higher_later" else 10
+                        L2 = min(L2, e2 - e - 1, n)
+                        if L2 >= 6:
+                            plant(q, r, int(rng.integers(0, n - L2 + 1)), L2, e2)
+                seqs += [q, r]
+    L = np.array([len(x) for x in seqs], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(L)])
+    prs = np.arange(len(seqs), dtype=np.int32).reshape(-1, 2)
+    return P.PairSet(np.concatenate(seqs), offs, prs, "planted one-lane")
+
+
+def test_one_lane_best_row_positions(sw):
+    """The one-lane forward pass keeps its best super-strip's input row in a
+    ring of four boundary buffers, copied aside when a later super-strip
+    would overwrite it; planted best cells at every distance from the end,
+    moving and staying picks and exact ties give the oracle's five outputs
+    (two seeds, both pair orders)."""
+    for seed in (41, 42):
+        ps = planted_one_lane_set(seed)
+        L = ps.lengths()
+        assert max(L.max(), 0) <= 1024
+        exp = expect(ps)
+        say("planted one-lane set %d: %d pairs, scores %d..%d" % (seed, ps.n_pairs, exp[:, 0].min(),
+                                                                   exp[:, 0].max()))
+        assert_same(gpu_align(sw, ps, flags=sw.VALIDATE), exp, ps, "planted one-lane %d" % seed)
+        rev = P.PairSet(ps.ascii, ps.offsets, ps.pairs[:, ::-1].copy(), "planted reversed")
+        assert_same(gpu_align(sw, rev, flags=sw.VALIDATE), expect(rev), rev, "planted reversed %d" % seed)
+
+
 def test_two_sets_match_one_set(sw):
     import torch
     ps = P.config_small(300)
