@@ -435,8 +435,8 @@ SW_API int sw_identity(const void* q_packed_dev, const int64_t* q_offsets_dev, i
  * alignment, then the identity and coverage filter that makes the edges of
  * the similarity graph), formed block by block with the next block made
  * ready while the current one aligns (section "Pre-blocking").
- * The queries are cut into contiguous blocks of block_queries queries (0: a
- * quarter of them).  For each block, sw_discover's pairs (k, min_shared,
+ * The queries are cut into contiguous blocks of block_queries queries (0:
+ * half of them).  For each block, sw_discover's pairs (k, min_shared,
  * mode as there; the mode filters use the global query index) are handed on
  * the device to the aligner (persistent form) and to sw_identity
  * (ani_permille, cov_permille as there), and the pairs it keeps are appended

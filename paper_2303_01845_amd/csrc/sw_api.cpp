@@ -1214,9 +1214,9 @@ int sw_search(const void* q_packed_dev, const int64_t* q_offsets_dev, int64_t n_
     }
     Device& d = *dp;
     DiscoverSpace& x = *xp;
-    // query blocks: block_queries queries each (0: a quarter of the queries);
+    // query blocks: block_queries queries each (0: half of the queries);
     // a block's pairs are at most its k-mer matches
-    const int64_t per_block = block_queries > 0 ? block_queries : std::max<int64_t>((n_q + 3) / 4, 1);
+    const int64_t per_block = block_queries > 0 ? block_queries : std::max<int64_t>((n_q + 1) / 2, 1);
     const std::vector<DiscoverRange> ranges = split_ranges(qp, (int64_t)1 << 62, per_block);
     int64_t need = 1;
     for (const DiscoverRange& r : ranges) {
