@@ -11,13 +11,14 @@
 // columns, and reports its matches and columns.
 //
 // One wave per pair, pairs handed out by a counter.  The box is swept in
-// strips of 64 R rows (R rows per lane): lane l owns rows 64 R s + R l ..
+// strips of 64 R rows (R rows per lane): lane l owns rows base + R l ..
 // + R - 1 and at step t computes column t - l of all of them, so the cells
 // above its first row come from lane l-1's previous two steps by lane
 // shuffles, and each further row reads the one above it in registers (R
-// cells per step share the shuffles and the loop overhead).  R is 1, 2 or 4,
-// the smallest that covers the box in one strip, else 4: a strip costs the
-// wave about N steps whatever its height.  The strip's bottom row (H and F) goes
+// cells per step share the shuffles and the loop overhead).  R is 4 for
+// every full 256-row strip and, for the box's last strip, the smallest of 1,
+// 2 or 4 that covers its rows: a strip costs the wave about N steps of R
+// cells per lane whatever its height.  The strip's bottom row (H and F) goes
 // to the wave's scratch row in global memory for the next strip; lane 0 reads
 // it 64 columns at a time, one chunk ahead, as it reads the reference codes.
 //
@@ -79,21 +80,23 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int src)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Sweep one box in strips of 64 R rows (R rows per lane) and return the key
-// of its last cell on the lane that owns it (kNegKey on the others).
+// Sweep rows row0 .. row1 - 1 of an M-row box in strips of 64 R rows (R rows
+// per lane; the rows above row0 were swept before, their last row in the
+// wave's scratch row) and return the key of the box's last cell on the lane
+// that owns it (kNegKey on the others, and when row1 < M).
 template <int R>
 __device__ __forceinline__ int64_t sweep_box(const int8_t* sub, int64_t* Hrow, int64_t* Frow,
                                              const uint32_t* qnib, const uint32_t* qhib, const uint32_t* rnib,
                                              const uint32_t* rhib, int64_t GO, int64_t GE, int M, int N,
-                                             int64_t Q0, int64_t R0, int lane, bool& bad_code)
+                                             int64_t Q0, int64_t R0, int lane, bool& bad_code, int row0, int row1)
 {
     constexpr int kStrip = 64 * R;
-    const int n_strips = (M + kStrip - 1) / kStrip;
+    const int n_strips = (row1 - row0 + kStrip - 1) / kStrip;
     int64_t fin = kNegKey;
     for (int st = 0; st < n_strips; ++st) {
         // lane l owns rows i0 .. i0 + R - 1 of the strip
-        const int base = st * kStrip;
-        const int rows = min(kStrip, M - base);
+        const int base = row0 + st * kStrip;
+        const int rows = min(kStrip, row1 - base);
         const int i0 = base + R * lane;
         const bool ok0 = R * lane < rows;
         const int8_t* subr[R];
@@ -111,7 +114,7 @@ __device__ __forceinline__ int64_t sweep_box(const int8_t* sub, int64_t* Hrow, i
             E[r] = kNegKey;
             Hleft[r] = kNegKey;
         }
-        int64_t diag_next = (lane == 0 && st == 0) ? kOriginKey : kNegKey;
+        int64_t diag_next = (lane == 0 && base == 0) ? kOriginKey : kNegKey;
         int64_t outH = kNegKey, outF = kNegKey;  // the lane's last row, handed to lane l+1
         uint32_t rc_prev = 0;
         // reference codes and the row above, 64 columns per chunk, one
@@ -119,7 +122,7 @@ __device__ __forceinline__ int64_t sweep_box(const int8_t* sub, int64_t* Hrow, i
         // and the wave's scratch row; their values are never used)
         uint32_t cur = code_at(rnib, rhib, R0 + lane);
         uint32_t nxt = code_at(rnib, rhib, R0 + 64 + lane);
-        const bool above = st > 0;
+        const bool above = base > 0;
         int64_t curH = kNegKey, curF = kNegKey, nxtH = kNegKey, nxtF = kNegKey;
         if (above) {
             curH = Hrow[lane];
@@ -185,7 +188,7 @@ __device__ __forceinline__ int64_t sweep_box(const int8_t* sub, int64_t* Hrow, i
                 }
                 outH = upH;
                 outF = upF;
-                if (lane == 63 && st + 1 < n_strips) {
+                if (lane == 63 && base + kStrip < M) {  // a full strip with rows below it
                     Hrow[j] = upH;
                     Frow[j] = upF;
                 }
@@ -281,16 +284,17 @@ __device__ __forceinline__ typename K::T sweep_box_exact(const typename K::T* st
                                                          typename K::T* Frow, const uint32_t* qnib,
                                                          const uint32_t* qhib, const uint32_t* rnib,
                                                          const uint32_t* rhib, int32_t go, int32_t ge, int M, int N,
-                                                         int64_t Q0, int64_t R0, int lane, bool& bad_code)
+                                                         int64_t Q0, int64_t R0, int lane, bool& bad_code, int row0,
+                                                         int row1)
 {
     typedef typename K::T T;
     constexpr int kStrip = 64 * R;
     const T GO = K::step(go), GE = K::step(ge);
-    const int n_strips = (M + kStrip - 1) / kStrip;
+    const int n_strips = (row1 - row0 + kStrip - 1) / kStrip;
     T fin = K::kNeg;
     for (int st = 0; st < n_strips; ++st) {
-        const int base = st * kStrip;
-        const int rows = min(kStrip, M - base);
+        const int base = row0 + st * kStrip;
+        const int rows = min(kStrip, row1 - base);
         const int i0 = base + R * lane;
         const bool ok0 = R * lane < rows;
         const T* tabr[R];
@@ -308,12 +312,12 @@ __device__ __forceinline__ typename K::T sweep_box_exact(const typename K::T* st
         }
         // lane 0's first diagonal: the origin (strip 0) or the column left of the box
         T diag_next = K::kNeg;
-        if (lane == 0) diag_next = st > 0 ? K::gap(go, ge, base - 1) : std::is_same<K, Key32>::value ? (T)0 : (T)kOriginKey;
+        if (lane == 0) diag_next = base > 0 ? K::gap(go, ge, base - 1) : std::is_same<K, Key32>::value ? (T)0 : (T)kOriginKey;
         T outH = K::kNeg, outF = K::kNeg;
         uint32_t rc_prev = 0;
         uint32_t cur = code_at(rnib, rhib, R0 + lane);
         uint32_t nxt = code_at(rnib, rhib, R0 + 64 + lane);
-        const bool above = st > 0;
+        const bool above = base > 0;
         T curH = 0, curF = 0, nxtH = 0, nxtF = 0;
         if (above) {
             curH = Hrow[lane];
@@ -374,7 +378,7 @@ __device__ __forceinline__ typename K::T sweep_box_exact(const typename K::T* st
                 }
                 outH = upH;
                 outF = upF;
-                if (lane == 63 && st + 1 < n_strips) {
+                if (lane == 63 && base + kStrip < M) {  // a full strip with rows below it
                     Hrow[j] = upH;
                     Frow[j] = upF;
                 }
@@ -460,24 +464,28 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
             continue;
         }
         const int64_t Q0 = qb + res.q_start, R0 = rb + res.r_start;
-        int64_t fin;
-        int fin_lane;
+        // rows per lane: 4 for every full 256-row strip, and for the box's
+        // last strip the fewest (1, 2 or 4) that cover its rows -- a strip
+        // costs the wave about N steps of R cells per lane whatever its height
+        const int m4 = M > 256 ? (M - 1) / 256 * 256 : 0;
+        const int r_last = M - m4 <= 64 ? 1 : (M - m4 <= 128 ? 2 : 4);
+        const int fin_lane = (M - 1 - m4) / r_last;
+        int64_t fin = kNegKey;
         if (box32_ok(M, N, a.go, a.ge)) {
             int32_t* H32 = reinterpret_cast<int32_t*>(Hrow);
             int32_t* F32 = reinterpret_cast<int32_t*>(Frow);
-            int32_t f32;
-            if (M <= 64) {
-                f32 = sweep_box_exact<1, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
-                                                R0, lane, bad_code);
-                fin_lane = M - 1;
-            } else if (M <= 128) {
-                f32 = sweep_box_exact<2, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
-                                                R0, lane, bad_code);
-                fin_lane = (M - 1) / 2;
-            } else {
-                f32 = sweep_box_exact<4, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
-                                                R0, lane, bad_code);
-                fin_lane = ((M - 1) % 256) / 4;
+            int32_t f32 = Key32::kNeg;
+            for (int seg = m4 > 0 ? 0 : 1; seg < 2; ++seg) {
+                const int r0 = seg == 0 ? 0 : m4, r1 = seg == 0 ? m4 : M, rr = seg == 0 ? 4 : r_last;
+                if (rr == 1)
+                    f32 = sweep_box_exact<1, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
+                                                    R0, lane, bad_code, r0, r1);
+                else if (rr == 2)
+                    f32 = sweep_box_exact<2, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
+                                                    R0, lane, bad_code, r0, r1);
+                else
+                    f32 = sweep_box_exact<4, Key32>(step32, H32, F32, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0,
+                                                    R0, lane, bad_code, r0, r1);
             }
             if (lane == fin_lane) {
                 rec.score = f32 >> kKey32ScoreShift;  // arithmetic: a negative score stays negative
@@ -493,27 +501,26 @@ __global__ void __launch_bounds__(64 * kIdentWavesPerBlock, 4) k_identity(IdentA
             continue;
         }
         const bool exact = box64x_ok(M, N, a.go, a.ge);
-        if (exact && M <= 64) {
-            fin = sweep_box_exact<1, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
-                                            bad_code);
-            fin_lane = M - 1;
-        } else if (exact && M <= 128) {
-            fin = sweep_box_exact<2, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
-                                            bad_code);
-            fin_lane = (M - 1) / 2;
-        } else if (exact) {
-            fin = sweep_box_exact<4, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0, lane,
-                                            bad_code);
-            fin_lane = ((M - 1) % 256) / 4;
-        } else if (M <= 64) {
-            fin = sweep_box<1>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
-            fin_lane = M - 1;
-        } else if (M <= 128) {
-            fin = sweep_box<2>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
-            fin_lane = (M - 1) / 2;
-        } else {
-            fin = sweep_box<4>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code);
-            fin_lane = ((M - 1) % 256) / 4;
+        for (int seg = m4 > 0 ? 0 : 1; seg < 2; ++seg) {
+            const int r0 = seg == 0 ? 0 : m4, r1 = seg == 0 ? m4 : M, rr = seg == 0 ? 4 : r_last;
+            if (exact && rr == 1)
+                fin = sweep_box_exact<1, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0,
+                                                lane, bad_code, r0, r1);
+            else if (exact && rr == 2)
+                fin = sweep_box_exact<2, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0,
+                                                lane, bad_code, r0, r1);
+            else if (exact)
+                fin = sweep_box_exact<4, Key64>(step64, Hrow, Frow, qnib, qhib, rnib, rhib, a.go, a.ge, M, N, Q0, R0,
+                                                lane, bad_code, r0, r1);
+            else if (rr == 1)
+                fin = sweep_box<1>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code, r0,
+                                   r1);
+            else if (rr == 2)
+                fin = sweep_box<2>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code, r0,
+                                   r1);
+            else
+                fin = sweep_box<4>(sub, Hrow, Frow, qnib, qhib, rnib, rhib, GO, GE, M, N, Q0, R0, lane, bad_code, r0,
+                                   r1);
         }
         if (lane == fin_lane) {
             if ((fin >> kScoreShift) > 0) {

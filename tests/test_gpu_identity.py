@@ -81,6 +81,30 @@ def test_tie_heavy_and_multi_strip(sw):
         assert np.array_equal(got, exp.astype(np.int32)), (go, ge)
 
 
+def test_last_strip_rows_per_lane(sw):
+    """Boxes just past one or two 256-row strips, whose last strip runs on 1,
+    2 or 4 rows per lane after full strips on 4, with 32-bit keys (boxes up to
+    511), exact 64-bit keys (larger ones) and the cut form (gap penalties too
+    large for the exact forms): the oracle's records."""
+    rng = np.random.default_rng(12)
+    alpha = list("ARNDCQEGHILKMFPSTWYV")
+    qs, rs = [], []
+    for M in (257, 258, 300, 320, 321, 350, 384, 385, 449, 511, 512, 513, 577, 640, 641, 700, 769):
+        for rate in (0.05, 0.3):
+            q = "".join(rng.choice(alpha, M))
+            r = list(q)
+            for i in np.flatnonzero(rng.random(M) < rate):
+                r[i] = str(rng.choice(alpha))
+            qs.append(q)
+            rs.append("".join(r))
+    ps = from_seqs(qs, rs)
+    for go, ge in ((11, 1), (10 ** 5, 10 ** 5)):
+        got, exp, aln = run_both(sw, ps, go, ge)
+        rows = aln[:, 2] - aln[:, 1] + 1
+        say("last-strip boxes go=%d ge=%d: rows %d..%d" % (go, ge, rows.min(), rows.max()))
+        assert np.array_equal(got, exp.astype(np.int32)), (go, ge)
+
+
 def test_long_boxes(sw):
     rng = np.random.default_rng(8)
     L = "ARNDCQEGHILKMFPSTWYV"
